@@ -1,0 +1,172 @@
+"""Benchmark of the neural-SDF collision hot path on one MI355X.
+
+One step = one collide_project call over the whole 1M-vertex cloth: load the
+vertex, evaluate the 3->256x8->1 (skip into layer 5) softplus MLP, its reverse
+input gradient, the normal, the f < eps test and the move to the contact
+point, in place (Sec. 3.2, Eq. 1-3).  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--precision bf16]
+                  [--no-cpu-baseline] [--no-compare]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}  # MI355X dense MFMA
+
+
+def flops_per_point(spec) -> int:
+    """Algorithmic work of forward + one reverse sweep: 4 * sum_l K_l * width_l
+    (every multiply-add of every affine map, counted twice for the two sweeps)."""
+    from paper_2110_01614_amd import inputs as I
+    return 4 * sum(o * i for o, i in I.layer_shapes(spec))
+
+
+def mfma_flops_per_point(spec) -> int:
+    """The part of the work in the K >= 64 hidden contractions (the MFMA kernels)."""
+    from paper_2110_01614_amd import inputs as I
+    sh = I.layer_shapes(spec)
+    return 4 * sum(o * min(i, spec.widths[0]) for o, i in sh[1:-1])
+
+
+def time_steps(net, X, eps, steps, warmup, torch):
+    for _ in range(warmup):
+        net.collide_project(X, eps, want=())
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        net.collide_project(X, eps, want=())
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]  # ms, one launch each
+    return wall, per
+
+
+def accuracy(spec, params, pts, net, torch, n=4096, eps=0.005):
+    import oracle
+    idx = np.random.default_rng(3).choice(len(pts), n, replace=False)
+    ref = oracle.collide_project(spec, params, pts[idx], eps)
+    X = torch.from_numpy(pts[idx]).cuda()
+    f, g = net.query_grad(X)
+    torch.cuda.synchronize()
+    f, g = f.cpu().numpy(), g.cpu().numpy().astype(np.float64)
+    ferr = np.abs(f - ref["sdf"])
+    cr = np.linalg.norm(np.cross(g, ref["grad"]), axis=1)
+    ang = np.arctan2(cr, np.einsum("ij,ij->i", g, ref["grad"]))
+    return {"sdf_max": float(ferr.max()), "sdf_p99": float(np.quantile(ferr, 0.99)),
+            "angle_max_rad": float(ang.max()), "angle_p99_rad": float(np.quantile(ang, 0.99)),
+            "sample": n}
+
+
+def cpu_baseline(spec, params, pts, target_s=10.0):
+    """The FP64 oracle (untuned) on the host cores, on a bounded sample."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    n0 = 1024
+    t = time.perf_counter()
+    oracle.collide_project(spec, params, pts[:n0], 0.005)
+    dt = time.perf_counter() - t
+    n = int(min(len(pts), max(n0, n0 * target_s / max(dt, 1e-3))))
+    t = time.perf_counter()
+    oracle.collide_project(spec, params, pts[:n], 0.005)
+    dt = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {"value": n / dt, "unit": "points/s", "cores": min(threads, cores), "kind": "oracle",
+            "sample": "first %d of the 1M cloth vertices, FP64 forward + reverse + project, %.1f s" % (n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the collision path shards across GPUs with no exchange "
+              "(each GPU takes a contiguous slice of vertices), so only --gpus 1 is run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2110_01614_amd import inputs as I
+    if not os.path.exists(os.path.join(ROOT, "paper_2110_01614_amd", "libsdfcollide.so")):
+        from paper_2110_01614_amd import build as b
+        b.build()
+    from paper_2110_01614_amd import binding as B
+
+    spec, params, pts, eps = I.workload_inputs("cloth1m")
+    n = len(pts)
+    fpp = flops_per_point(spec)
+    X0 = torch.from_numpy(pts).cuda()
+    results = {}
+    order = [args.precision] + ([] if args.no_compare else
+                                [p for p in ("fp32", "fp16", "bf16") if p != args.precision])
+    for prec in order:
+        net = B.SdfNet(spec, params, prec)
+        X = X0.clone()
+        steps = args.steps if prec != "fp32" else max(3, min(args.steps, 10))
+        wall, per = time_steps(net, X, eps, steps, args.warmup if prec != "fp32" else 2, torch)
+        avg_ms = float(np.mean(per))
+        r = {"ms_per_step": wall * 1e3 / steps, "kernel_ms_mean": avg_ms,
+             "kernel_ms_median": float(np.median(per)), "points_per_s": n * steps / wall,
+             "tflops": fpp * n / (avg_ms * 1e-3) / 1e12}
+        r["mfma_frac"] = r["tflops"] / PEAK_TFLOPS[prec]
+        if not args.no_accuracy:
+            r["accuracy_vs_fp64"] = accuracy(spec, params, pts, net, torch)
+        results[prec] = r
+        net.close()
+        del X
+
+    head = results[args.precision]
+    out = {
+        "metric": "SDF+normal queries/s at 1M pts, BF16 vs FP32, at stated error; MFMA util %",
+        "value": head["points_per_s"],
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "cloth1m: 1000x1000 cloth grid (spacing 2e-3, z = 0.1 sin noise, "
+                               "N(0,0.01) jitter, seed 2) through 3->256x8->1 softplus(beta=100) "
+                               "MLP, input re-fed at layer 5, N(0,0.02) weights seed 0; "
+                               "collide_project in place, eps 0.005",
+                   "points": n, "flops_per_point": fpp, "launch": "1 kernel / step, 64 points "
+                   "per 256-thread workgroup"},
+        "roofline": {"bound": "mfma", "achieved": head["tflops"], "peak": PEAK_TFLOPS[args.precision],
+                     "unit": "TFLOP/s", "frac": head["mfma_frac"], "traffic": None},
+        "precisions": results,
+        "paper_context": "Table 1 / abstract: ~1M queries in ~300 ms on a Tesla T4 (TensorFlow, "
+                         "Fourier features + 4 or 8 FC x 256, ReLU)",
+    }
+    if "fp32" in results:
+        out["speedup_vs_fp32"] = head["points_per_s"] / results["fp32"]["points_per_s"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, params, pts)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,114 @@
+/*
+ * sdfcollide.h -- C ABI of the MI355X (gfx950) neural-SDF collision library.
+ *
+ * Method: Bertiche, Madadi, Escalera, "Neural Implicit Surfaces for Efficient
+ * and Accurate Collisions in Physically Based Simulations" (arXiv 2110.01614).
+ * A learned signed-distance MLP f: R^3 -> R (Sec. 3.1, Eq. 1) is evaluated at
+ * every cloth vertex together with its analytic input gradient obtained by
+ * back-propagation (Sec. 3.2); the normal is N = grad f / |grad f| (Eq. 2), a
+ * vertex collides when f(p) < eps (Sec. 3.2), and a colliding vertex is moved
+ * along N by (eps - f(p)), the contact-point offset of Eq. 3.  Interior is
+ * negative, so the gradient points outward (Sec. 3.2).
+ *
+ * Conventions shared by every entry point:
+ *  - Array arguments are DEVICE pointers (hipMalloc'd or torch CUDA tensors),
+ *    caller-owned, contiguous, 4-byte aligned.  Points are float32 [n][3]
+ *    array-of-structures.  The library never frees or retains them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued asynchronously; device faults surface at the caller's sync.
+ *  - Return value: SDF_OK (0) or a negative SDF_E* code.  Argument checks run
+ *    on the host before anything is launched; on failure nothing is launched
+ *    and sdf_last_error() (thread-local) describes the problem.
+ *  - n == 0 returns SDF_OK and launches nothing.
+ *  - Numerical policy: outputs are float32 whatever the internal precision; a
+ *    NaN f is not a hit; |grad f| == 0 gives N = 0 and the vertex is not
+ *    moved; a vertex that is not moved keeps its exact bit pattern.
+ *  - The handle is immutable after creation: concurrent calls with one handle
+ *    on different streams are allowed; sdf_net_destroy needs the caller to
+ *    have synchronised every stream that used the handle.
+ */
+#ifndef SDFCOLLIDE_H
+#define SDFCOLLIDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SDF_OK = 0,
+  SDF_EINVAL = -1,       /* bad argument (null pointer, n < 0, non-finite eps, ...) */
+  SDF_EUNSUPPORTED = -2, /* a network shape or precision this build has no kernel for */
+  SDF_ENOMEM = -3,       /* device allocation failed in sdf_net_create */
+  SDF_EDEVICE = -4       /* a HIP runtime call or launch failed */
+};
+
+/* Operand precision of the hidden-layer contractions (MFMA, FP32 accumulate).
+ * Layer 1 (K = 3), the skip x-columns, the output layer, the normalisation
+ * and the projection always run in FP32. */
+enum { SDF_FP32 = 0, SDF_BF16 = 1, SDF_FP16 = 2 };
+
+#define SDF_MAX_HIDDEN 16
+
+/* Network shape (Sec. 3.1: one MLP per rigid object).  in_dim is 3, out_dim 1.
+ * Hidden layer l (1-based) has width[l-1] units and softplus activation
+ * softplus_beta(z) = log(1 + exp(beta z)) / beta.  If skip_layer = s > 0,
+ * hidden layer s takes [h_{s-1}; x] (hidden features first, then x, y, z).
+ * This build has kernels for equal hidden widths of 64, 128 or 256, depth
+ * 2..8, skip 0 or 2..depth; other shapes return SDF_EUNSUPPORTED. */
+typedef struct {
+  int32_t n_hidden;
+  int32_t width[SDF_MAX_HIDDEN];
+  int32_t skip_layer;
+  float beta;
+  int32_t precision;
+} sdf_net_desc;
+
+typedef struct sdf_net sdf_net; /* opaque; owns device copies of packed weights */
+
+/* Number of float32 parameters of `desc` in the flat layout below, or -1 if
+ * the description is malformed.  Flat layout (the concatenation of every
+ * nn.Linear weight then bias): for l = 1..L, W_l row-major [width_l][K_l] then
+ * b_l[width_l], K_1 = 3, K_l = width_{l-1} (+3 at the skip layer); then
+ * w_o[width_L], b_o. */
+int64_t sdf_param_count(const sdf_net_desc* desc);
+
+/* Packs `params_host` (HOST float32, n_params values, copied) for `device`
+ * and returns a handle in *out.  Allocates all device memory the queries will
+ * ever need (no allocation happens on the query path).  Errors: SDF_EINVAL
+ * (null pointer, bad shape, n_params mismatch, non-finite beta or params),
+ * SDF_EUNSUPPORTED, SDF_ENOMEM, SDF_EDEVICE. */
+int sdf_net_create(const sdf_net_desc* desc, const float* params_host, size_t n_params,
+                   int device, sdf_net** out);
+
+/* Frees the handle and its device memory.  NULL is ignored. */
+int sdf_net_destroy(sdf_net* net);
+
+/* f(p) for n points (Sec. 3.1, Eq. 1).  pts: device float32 [n][3] (read);
+ * sdf: device float32 [n] (written).  pts and sdf must not overlap. */
+int sdf_query(const sdf_net* net, const float* pts, int64_t n, float* sdf, void* stream);
+
+/* f(p) and the unnormalised input gradient grad f(p) by reverse-mode
+ * back-propagation (Sec. 3.2).  sdf: device float32 [n] or NULL; grad: device
+ * float32 [n][3] (required).  Outputs must not overlap pts. */
+int sdf_query_grad(const sdf_net* net, const float* pts, int64_t n, float* sdf, float* grad,
+                   void* stream);
+
+/* The collision step of Sec. 3.2 for every vertex, in place: detect f < eps
+ * (strict), N = grad f/|grad f| (Eq. 2), move hits to p + (eps - f) N (Eq. 3).
+ * pts: device float32 [n][3] (read and overwritten).  sdf (f before the move,
+ * [n]), normal ([n][3]) and hit (uint8 [n], 1 = f < eps) are optional device
+ * outputs (NULL to skip) that must not overlap pts.  eps must be finite. */
+int collide_project(const sdf_net* net, float* pts, int64_t n, float eps, float* sdf,
+                    float* normal, uint8_t* hit, void* stream);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* sdf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDFCOLLIDE_H */

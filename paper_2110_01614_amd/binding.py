@@ -1,0 +1,186 @@
+"""Thin ctypes binding of libsdfcollide.so (declared in include/sdfcollide.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels.
+Functions keep the C names; ``SdfNet`` is a small owner of a handle that
+takes torch CUDA tensors (PyTorch supplies device memory and the stream).
+Importing this module loads the library and raises if it is missing -- there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsdfcollide.so")
+
+SDF_OK, SDF_EINVAL, SDF_EUNSUPPORTED, SDF_ENOMEM, SDF_EDEVICE = 0, -1, -2, -3, -4
+SDF_FP32, SDF_BF16, SDF_FP16 = 0, 1, 2
+SDF_MAX_HIDDEN = 16
+PRECISIONS = {"fp32": SDF_FP32, "bf16": SDF_BF16, "fp16": SDF_FP16}
+
+
+class sdf_net_desc(ctypes.Structure):
+    _fields_ = [("n_hidden", ctypes.c_int32),
+                ("width", ctypes.c_int32 * SDF_MAX_HIDDEN),
+                ("skip_layer", ctypes.c_int32),
+                ("beta", ctypes.c_float),
+                ("precision", ctypes.c_int32)]
+
+
+class SdfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("sdfcollide error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsdfcollide.so is not built (run paper_2110_01614_amd.build); "
+                          "there is no fallback implementation")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float
+    desc_p = ctypes.POINTER(sdf_net_desc)
+    lib.sdf_param_count.restype = i64
+    lib.sdf_param_count.argtypes = [desc_p]
+    lib.sdf_net_create.restype = ctypes.c_int
+    lib.sdf_net_create.argtypes = [desc_p, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t,
+                                   ctypes.c_int, ctypes.POINTER(vp)]
+    lib.sdf_net_destroy.restype = ctypes.c_int
+    lib.sdf_net_destroy.argtypes = [vp]
+    lib.sdf_query.restype = ctypes.c_int
+    lib.sdf_query.argtypes = [vp, vp, i64, vp, vp]
+    lib.sdf_query_grad.restype = ctypes.c_int
+    lib.sdf_query_grad.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.collide_project.restype = ctypes.c_int
+    lib.collide_project.argtypes = [vp, vp, i64, f32, vp, vp, vp, vp]
+    lib.sdf_last_error.restype = ctypes.c_char_p
+    lib.sdf_last_error.argtypes = []
+    return lib
+
+
+lib = _load()
+
+
+def sdf_last_error() -> str:
+    return lib.sdf_last_error().decode()
+
+
+def _check(rc):
+    if rc != SDF_OK:
+        raise SdfError(rc, sdf_last_error())
+    return rc
+
+
+def make_desc(widths, skip=0, beta=100.0, precision="fp32") -> sdf_net_desc:
+    d = sdf_net_desc()
+    d.n_hidden = len(widths)
+    for i, w in enumerate(widths):
+        d.width[i] = int(w)
+    d.skip_layer = int(skip)
+    d.beta = float(beta)
+    d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return d
+
+
+def sdf_param_count(desc: sdf_net_desc) -> int:
+    return int(lib.sdf_param_count(ctypes.byref(desc)))
+
+
+def sdf_net_create(desc: sdf_net_desc, params_host, device: int = 0):
+    """params_host: contiguous float32 numpy array (host).  Returns a handle (int)."""
+    import numpy as np
+    p = np.ascontiguousarray(params_host, dtype=np.float32)
+    h = ctypes.c_void_p()
+    _check(lib.sdf_net_create(ctypes.byref(desc), p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                              p.size, int(device), ctypes.byref(h)))
+    return h.value
+
+
+def sdf_net_destroy(handle):
+    return _check(lib.sdf_net_destroy(handle))
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+def sdf_query(handle, pts, n, sdf, stream=None):
+    return _check(lib.sdf_query(handle, _ptr(pts), int(n), _ptr(sdf), _stream(stream)))
+
+
+def sdf_query_grad(handle, pts, n, sdf, grad, stream=None):
+    return _check(lib.sdf_query_grad(handle, _ptr(pts), int(n), _ptr(sdf), _ptr(grad), _stream(stream)))
+
+
+def collide_project(handle, pts, n, eps, sdf=None, normal=None, hit=None, stream=None):
+    return _check(lib.collide_project(handle, _ptr(pts), int(n), float(eps), _ptr(sdf), _ptr(normal),
+                                      _ptr(hit), _stream(stream)))
+
+
+class SdfNet:
+    """Owner of one packed network on one device; methods take torch CUDA tensors."""
+
+    def __init__(self, spec, params, precision="fp32", device=0):
+        self.spec = spec
+        self.precision = precision
+        self.device = device
+        self.desc = make_desc(spec.widths, spec.skip, spec.beta, precision)
+        self.handle = sdf_net_create(self.desc, params, device)
+
+    def close(self):
+        if self.handle:
+            sdf_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _pts(pts):
+        import torch
+        if not (pts.is_cuda and pts.dtype == torch.float32 and pts.is_contiguous()
+                and pts.dim() == 2 and pts.shape[1] == 3):
+            raise ValueError("pts must be a contiguous float32 CUDA tensor of shape [n, 3]")
+        return pts
+
+    def query(self, pts, out=None):
+        import torch
+        pts = self._pts(pts)
+        out = torch.empty(pts.shape[0], device=pts.device, dtype=torch.float32) if out is None else out
+        sdf_query(self.handle, pts, pts.shape[0], out)
+        return out
+
+    def query_grad(self, pts, sdf=None, grad=None):
+        import torch
+        pts = self._pts(pts)
+        n = pts.shape[0]
+        sdf = torch.empty(n, device=pts.device, dtype=torch.float32) if sdf is None else sdf
+        grad = torch.empty(n, 3, device=pts.device, dtype=torch.float32) if grad is None else grad
+        sdf_query_grad(self.handle, pts, n, sdf, grad)
+        return sdf, grad
+
+    def collide_project(self, pts, eps, want=("sdf", "normal", "hit")):
+        """In place on pts; returns the requested optional outputs."""
+        import torch
+        pts = self._pts(pts)
+        n = pts.shape[0]
+        outs = {}
+        if "sdf" in want:
+            outs["sdf"] = torch.empty(n, device=pts.device, dtype=torch.float32)
+        if "normal" in want:
+            outs["normal"] = torch.empty(n, 3, device=pts.device, dtype=torch.float32)
+        if "hit" in want:
+            outs["hit"] = torch.empty(n, device=pts.device, dtype=torch.uint8)
+        collide_project(self.handle, pts, n, eps, outs.get("sdf"), outs.get("normal"), outs.get("hit"))
+        return outs

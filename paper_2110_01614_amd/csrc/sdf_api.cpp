@@ -1,0 +1,403 @@
+// sdf_api.cpp -- C ABI of the gfx950 neural-SDF collision library: argument
+// checks, weight packing and kernel dispatch.  Declared in
+// include/sdfcollide.h, which states the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sdfcollide.h"
+#include "sdf_device.hpp"
+
+namespace sdfc {
+template <int W, int PREC, int MODE>
+__global__ void sdf_k16(const KArgs a);
+template <int W, int MODE>
+__global__ void sdf_k32(const KArgs a);
+}  // namespace sdfc
+
+using namespace sdfc;
+
+struct sdf_net {
+  sdf_net_desc desc;
+  int device = 0;
+  int W = 0, L = 0, skip = 0, prec = 0;
+  float bo = 0.0f;
+  unsigned char* d_stream = nullptr;
+  size_t stream_bytes = 0;
+  int chunks_per_layer = 0;
+  float* d_small = nullptr;
+  float* d_scratch = nullptr;  // FP32 sigma stack, one slot per resident workgroup
+  int slots = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SDF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Checks the shape; fills W, L, skip.  Returns SDF_OK or an error code.
+int check_desc(const sdf_net_desc* d, int* W, int* L, int* skip) {
+  if (!d) return fail(SDF_EINVAL, "desc is NULL");
+  if (d->n_hidden < 1 || d->n_hidden > SDF_MAX_HIDDEN)
+    return fail(SDF_EINVAL, "n_hidden must be in [1, 16]");
+  for (int i = 0; i < d->n_hidden; ++i)
+    if (d->width[i] < 1) return fail(SDF_EINVAL, "widths must be positive");
+  if (d->skip_layer == 1 || d->skip_layer < 0 || d->skip_layer > d->n_hidden)
+    return fail(SDF_EINVAL, "skip_layer must be 0 or in [2, n_hidden]");
+  if (!std::isfinite(d->beta) || d->beta <= 0.0f) return fail(SDF_EINVAL, "beta must be finite and > 0");
+  if (d->precision != SDF_FP32 && d->precision != SDF_BF16 && d->precision != SDF_FP16)
+    return fail(SDF_EINVAL, "unknown precision");
+  *W = d->width[0];
+  *L = d->n_hidden;
+  *skip = d->skip_layer;
+  return SDF_OK;
+}
+
+int check_supported(int W, const sdf_net_desc* d) {
+  for (int i = 1; i < d->n_hidden; ++i)
+    if (d->width[i] != W) return fail(SDF_EUNSUPPORTED, "hidden widths must be equal");
+  if (W != 64 && W != 128 && W != 256) return fail(SDF_EUNSUPPORTED, "width must be 64, 128 or 256");
+  if (d->n_hidden < 2 || d->n_hidden > kLMax) return fail(SDF_EUNSUPPORTED, "depth must be in [2, 8]");
+  return SDF_OK;
+}
+
+int64_t count_params(const sdf_net_desc* d) {
+  int64_t c = 0;
+  int prev = 3;
+  for (int l = 1; l <= d->n_hidden; ++l) {
+    const int w = d->width[l - 1];
+    const int k = prev + (l == d->skip_layer ? 3 : 0);
+    c += (int64_t)w * k + w;
+    prev = w;
+  }
+  return c + prev + 1;
+}
+
+// Host view of the flat parameters.
+struct Net {
+  int W, L, skip;
+  std::vector<const float*> Wl, bl;  // index l = 1..L
+  const float* wo;
+  float bo;
+  int K(int l) const { return (l == 1 ? 3 : W) + (l == skip ? 3 : 0); }
+};
+
+Net view(const float* P, int W, int L, int skip) {
+  Net n{W, L, skip, std::vector<const float*>(L + 1), std::vector<const float*>(L + 1), nullptr, 0.0f};
+  const float* q = P;
+  for (int l = 1; l <= L; ++l) {
+    n.Wl[l] = q;
+    q += (size_t)W * n.K(l);
+    n.bl[l] = q;
+    q += W;
+  }
+  n.wo = q;
+  n.bo = q[W];
+  return n;
+}
+
+uint16_t to_bf16(float v) {  // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+uint16_t to_fp16(float v) {  // round to nearest even, saturating to +-inf on overflow
+  return __builtin_bit_cast(uint16_t, (_Float16)v);
+}
+
+// Per-layer power-of-two scales of the reverse-sweep vectors d_l (16-bit
+// paths): S_l ~ -log2(rms(d_l)), estimated from the weights alone with
+// rms(d_L) ~ rms(w_o)/2 and rms(d_{l-1}) ~ rms(d_l) |W_l|_F / sqrt(K) / 2.
+std::vector<int> reverse_scales(const Net& n) {
+  std::vector<int> S(n.L + 1, 0);
+  double ss = 0.0;
+  for (int j = 0; j < n.W; ++j) ss += (double)n.wo[j] * n.wo[j];
+  double rms = 0.5 * std::sqrt(ss / n.W) + 1e-30;
+  for (int l = n.L; l >= 1; --l) {
+    S[l] = (int)std::lround(-std::log2(rms));
+    if (S[l] > 100) S[l] = 100;
+    if (S[l] < -100) S[l] = -100;
+    if (l > 1) {
+      double fro = 0.0;
+      const int K = n.K(l);
+      for (int j = 0; j < n.W; ++j)
+        for (int k = 0; k < n.W; ++k) fro += (double)n.Wl[l][(size_t)j * K + k] * n.Wl[l][(size_t)j * K + k];
+      rms = 0.5 * rms * std::sqrt(fro / n.W) + 1e-30;
+    }
+  }
+  return S;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sdf_param_count(const sdf_net_desc* desc) {
+  int W, L, skip;
+  if (check_desc(desc, &W, &L, &skip) != SDF_OK) return -1;
+  return count_params(desc);
+}
+
+const char* sdf_last_error(void) { return g_err.c_str(); }
+
+int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_params, int device,
+                   sdf_net** out) {
+  g_err.clear();
+  if (!out) return fail(SDF_EINVAL, "out is NULL");
+  *out = nullptr;
+  int W, L, skip;
+  int rc = check_desc(desc, &W, &L, &skip);
+  if (rc) return rc;
+  if (!params) return fail(SDF_EINVAL, "params is NULL");
+  if ((int64_t)n_params != count_params(desc))
+    return fail(SDF_EINVAL, "n_params is " + std::to_string(n_params) + ", expected " +
+                                std::to_string(count_params(desc)));
+  for (size_t i = 0; i < n_params; ++i)
+    if (!std::isfinite(params[i])) return fail(SDF_EINVAL, "params must be finite");
+  rc = check_supported(W, desc);
+  if (rc) return rc;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(SDF_EINVAL, "no such device");
+
+  const Net n = view(params, W, L, skip);
+  const int prec = desc->precision;
+  const double kappa = (double)desc->beta / std::log(2.0);  // beta * log2(e)
+  std::vector<int> S = (prec == SDF_FP32) ? std::vector<int>(L + 1, 0) : reverse_scales(n);
+
+  // ---- small FP32 block ----
+  const SmallLayout SL{W};
+  std::vector<float> sm(SL.floats(), 0.0f);
+  for (int j = 0; j < W; ++j) {
+    const float* w1 = n.Wl[1] + (size_t)j * n.K(1);
+    for (int c = 0; c < 3; ++c) {
+      sm[SL.l1() + 4 * j + c] = (float)(kappa * w1[c]);
+      sm[SL.l1g() + 4 * j + c] = (float)std::ldexp((double)w1[c], -S[1]);
+    }
+    sm[SL.l1() + 4 * j + 3] = (float)(kappa * n.bl[1][j]);
+    if (skip) {
+      const float* ws = n.Wl[skip] + (size_t)j * n.K(skip) + W;
+      for (int c = 0; c < 3; ++c) {
+        sm[SL.skf() + 4 * j + c] = (float)(kappa * ws[c]);
+        sm[SL.skg() + 4 * j + c] = (float)std::ldexp((double)ws[c], -S[skip]);
+      }
+    }
+    sm[SL.wof() + j] = (float)(n.wo[j] / kappa);
+    sm[SL.wob() + j] = (float)std::ldexp((double)n.wo[j], S[L]);
+    for (int l = 2; l <= L; ++l) sm[SL.bias(l) + j] = (float)(kappa * n.bl[l][j]);
+  }
+
+  // ---- fragment stream: forward W_2..W_L, then reverse W_L^T..W_2^T ----
+  std::vector<unsigned char> stream;
+  int cpl = 0;
+  auto emit16 = [&](auto at /* (row, col) -> float */) {
+    const int MT = W / 16, KB = W / 32;
+    for (int mt = 0; mt < MT; ++mt)
+      for (int kb = 0; kb < KB; ++kb)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int g = lane >> 4, row = lane & 15;
+          for (int e = 0; e < 8; ++e) {
+            const int col = 32 * kb + 16 * (e / 4) + 4 * g + (e % 4);
+            const float v = at(16 * mt + row, col);
+            const uint16_t h = (prec == SDF_BF16) ? to_bf16(v) : to_fp16(v);
+            stream.push_back((unsigned char)(h & 0xff));
+            stream.push_back((unsigned char)(h >> 8));
+          }
+        }
+  };
+  auto emit32 = [&](auto at) {
+    const int MT = W / 16;
+    for (int mt = 0; mt < MT; ++mt)
+      for (int m = 0; m < MT; ++m)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int g = lane >> 4, row = lane & 15;
+          for (int i = 0; i < 4; ++i) {
+            const float v = at(16 * mt + row, 16 * m + 4 * g + i);
+            unsigned char b[4];
+            std::memcpy(b, &v, 4);
+            stream.insert(stream.end(), b, b + 4);
+          }
+        }
+  };
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int step = 0; step < L - 1; ++step) {
+      const int l = pass == 0 ? 2 + step : L - step;
+      const float* Wl = n.Wl[l];
+      const int K = n.K(l);
+      const float sc = (float)std::ldexp(1.0, S[l - 1] - S[l]);
+      auto fwd = [&](int r, int c) { return Wl[(size_t)r * K + c]; };
+      auto rev = [&](int r, int c) { return Wl[(size_t)c * K + r] * sc; };
+      if (prec == SDF_FP32) {
+        if (pass == 0) emit32(fwd); else emit32(rev);
+      } else {
+        if (pass == 0) emit16(fwd); else emit16(rev);
+      }
+    }
+  }
+  if (prec != SDF_FP32) {
+    // a 16-bit value that overflowed would make every gradient through it infinite
+    for (size_t i = 0; i + 1 < stream.size(); i += 2) {
+      const uint16_t h = (uint16_t)(stream[i] | (stream[i + 1] << 8));
+      const bool inf = (prec == SDF_BF16) ? ((h & 0x7f80) == 0x7f80) : ((h & 0x7c00) == 0x7c00);
+      if (inf) return fail(SDF_EUNSUPPORTED, "a weight does not fit the 16-bit operand range");
+    }
+  }
+  const size_t layer_bytes = (size_t)(W / 16) * (prec == SDF_FP32 ? W / 16 : W / 32) * kFrag;
+  const size_t chunk = layer_bytes < 32768 ? layer_bytes : 32768;
+  cpl = (int)(layer_bytes / chunk);
+
+  int prev_dev = 0;
+  (void)hipGetDevice(&prev_dev);
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  sdf_net* net = new sdf_net();
+  net->desc = *desc;
+  net->device = device;
+  net->W = W;
+  net->L = L;
+  net->skip = skip;
+  net->prec = prec;
+  net->bo = n.bo;
+  net->stream_bytes = stream.size();
+  net->chunks_per_layer = cpl;
+  auto cleanup = [&](int code, const std::string& msg) {
+    sdf_net_destroy(net);
+    (void)hipSetDevice(prev_dev);
+    return fail(code, msg);
+  };
+  if (hipMalloc(&net->d_stream, stream.size()) != hipSuccess) return cleanup(SDF_ENOMEM, "hipMalloc(stream)");
+  if (hipMalloc(&net->d_small, sm.size() * 4) != hipSuccess) return cleanup(SDF_ENOMEM, "hipMalloc(small)");
+  if (hipMemcpy(net->d_stream, stream.data(), stream.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(net->d_small, sm.data(), sm.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(SDF_EDEVICE, "hipMemcpy of packed weights");
+  if (prec == SDF_FP32) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+      return cleanup(SDF_EDEVICE, "hipDeviceGetAttribute(CU count)");
+    net->slots = cus;  // one 4-wave workgroup per CU (LDS-bound)
+    const size_t bytes = (size_t)net->slots * (kLMax - 1) * 4 * (W / 16) * 64 * 16;
+    if (hipMalloc(&net->d_scratch, bytes) != hipSuccess) return cleanup(SDF_ENOMEM, "hipMalloc(scratch)");
+  }
+  (void)hipSetDevice(prev_dev);
+  *out = net;
+  return SDF_OK;
+}
+
+int sdf_net_destroy(sdf_net* net) {
+  if (!net) return SDF_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(net->device);
+  if (net->d_stream) (void)hipFree(net->d_stream);
+  if (net->d_small) (void)hipFree(net->d_small);
+  if (net->d_scratch) (void)hipFree(net->d_scratch);
+  (void)hipSetDevice(prev);
+  delete net;
+  return SDF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <int MODE>
+hipError_t launch(const sdf_net* net, const KArgs& a, hipStream_t s) {
+  const int W = net->W;
+  dim3 block(kBlock);
+  if (net->prec == SDF_FP32) {
+    dim3 grid((unsigned)(a.ntiles < net->slots ? a.ntiles : net->slots));
+#define K32(WW) \
+  if (W == WW) hipLaunchKernelGGL((sdf_k32<WW, MODE>), grid, block, 0, s, a);
+    K32(64) K32(128) K32(256)
+#undef K32
+  } else {
+    dim3 grid((unsigned)a.ntiles);
+#define K16(WW, PP) \
+  if (W == WW && net->prec == (PP == PREC_BF16 ? SDF_BF16 : SDF_FP16)) \
+    hipLaunchKernelGGL((sdf_k16<WW, PP, MODE>), grid, block, 0, s, a);
+    K16(64, PREC_BF16) K16(128, PREC_BF16) K16(256, PREC_BF16)
+    K16(64, PREC_FP16) K16(128, PREC_FP16) K16(256, PREC_FP16)
+#undef K16
+  }
+  return hipGetLastError();
+}
+
+bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
+
+// Shared checks and launch for the three query entry points.
+template <int MODE>
+int run(const sdf_net* net, const float* pts_in, float* pts_out, int64_t n, float eps, float* sdf,
+        float* grad, float* normal, uint8_t* hit, void* stream) {
+  g_err.clear();
+  if (!net) return fail(SDF_EINVAL, "net is NULL");
+  if (n < 0) return fail(SDF_EINVAL, "n < 0");
+  if (!pts_in) return fail(SDF_EINVAL, "pts is NULL");
+  if (MODE == MODE_QUERY && !sdf) return fail(SDF_EINVAL, "sdf is NULL");
+  if (MODE == MODE_GRAD && !grad) return fail(SDF_EINVAL, "grad is NULL");
+  if (MODE == MODE_PROJECT && !std::isfinite(eps)) return fail(SDF_EINVAL, "eps must be finite");
+  if (!aligned4(pts_in) || !aligned4(sdf) || !aligned4(grad) || !aligned4(normal))
+    return fail(SDF_EINVAL, "float arrays must be 4-byte aligned");
+  if (n > ((int64_t)1 << 40)) return fail(SDF_EINVAL, "n too large");
+  if (n == 0) return SDF_OK;
+  const int64_t tiles = (n + kPtsPerBlock - 1) / kPtsPerBlock;
+  if (tiles > 0x7fffffff) return fail(SDF_EINVAL, "n too large");
+  KArgs a{};
+  a.pts_in = pts_in;
+  a.pts_out = pts_out;
+  a.n = n;
+  a.sdf = sdf;
+  a.grad = grad;
+  a.normal = normal;
+  a.hit = hit;
+  a.eps = eps;
+  a.bo = net->bo;
+  a.stream = net->d_stream;
+  a.small = net->d_small;
+  a.scratch = net->d_scratch;
+  a.L = net->L;
+  a.skip = net->skip;
+  a.nch = (net->L - 1) * net->chunks_per_layer * (MODE == MODE_QUERY ? 1 : 2);
+  a.ntiles = (int)tiles;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (prev != net->device) (void)hipSetDevice(net->device);
+  const hipError_t e = launch<MODE>(net, a, (hipStream_t)stream);
+  if (prev != net->device) (void)hipSetDevice(prev);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return SDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdf_query(const sdf_net* net, const float* pts, int64_t n, float* sdf, void* stream) {
+  return run<MODE_QUERY>(net, pts, nullptr, n, 0.0f, sdf, nullptr, nullptr, nullptr, stream);
+}
+
+int sdf_query_grad(const sdf_net* net, const float* pts, int64_t n, float* sdf, float* grad,
+                   void* stream) {
+  return run<MODE_GRAD>(net, pts, nullptr, n, 0.0f, sdf, grad, nullptr, nullptr, stream);
+}
+
+int collide_project(const sdf_net* net, float* pts, int64_t n, float eps, float* sdf,
+                    float* normal, uint8_t* hit, void* stream) {
+  return run<MODE_PROJECT>(net, pts, pts, n, eps, sdf, nullptr, normal, hit, stream);
+}
+
+}  // extern "C"

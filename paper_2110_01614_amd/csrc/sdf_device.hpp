@@ -1,0 +1,170 @@
+// sdf_device.hpp -- gfx950 device helpers for the neural-SDF kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sdf_layout.hpp"
+
+namespace sdfc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+enum { MODE_QUERY = 0, MODE_GRAD = 1, MODE_PROJECT = 2 };
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2 };
+
+// Everything a launch needs; passed by value in the kernel argument segment.
+struct KArgs {
+  const float* pts_in;   // [n][3]
+  float* pts_out;        // [n][3] (collide_project: same as pts_in)
+  int64_t n;
+  float* sdf;            // [n] or null
+  float* grad;           // [n][3] or null
+  float* normal;         // [n][3] or null
+  uint8_t* hit;          // [n] or null
+  float eps;
+  float bo;              // output bias
+  const unsigned char* stream;  // packed fragments, forward then reverse
+  const float* small;    // SmallLayout block
+  float* scratch;        // FP32 kernels: per-slot sigma stack
+  int L;                 // hidden layers
+  int skip;              // 0 or 2..L
+  int nch;               // chunks streamed per tile
+  int ntiles;            // ceil(n / 64)
+};
+
+__device__ __forceinline__ unsigned lds_u32(const void* p) {
+  return (unsigned)(uintptr_t)(__attribute__((address_space(3))) const void*)p;
+}
+
+// One 16-byte-per-lane global->LDS copy; the wave's 64 lanes fill 1 KB at
+// the wave-uniform LDS byte address `lds` (lane i -> lds + 16 i).  Issued as
+// inline asm so the compiler's wait-count bookkeeping does not serialise the
+// prefetch: waits for these copies are placed by hand (vm_wait_barrier).
+__device__ __forceinline__ void dma16(const void* g, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds)
+               : "memory", "m0");
+}
+
+// Wait until at most N vector-memory operations of this wave are pending and
+// all of its LDS operations are done, then barrier the workgroup.
+template <int N>
+__device__ __forceinline__ void vm_wait_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"I"(N) : "memory");
+}
+
+// Copy chunk `c` of the weight stream into ring slot c % kNBuf.
+template <class G>
+__device__ __forceinline__ void issue_chunk(const unsigned char* stream, int c, unsigned ring,
+                                            int wave, int lane) {
+  const unsigned char* src = stream + (size_t)c * G::CHUNK + wave * 1024 + lane * 16;
+  const unsigned dst = ring + (unsigned)((c % kNBuf) * G::CHUNK) + wave * 1024;
+#pragma unroll
+  for (int j = 0; j < G::LPC; ++j) dma16(src + j * 4096, dst + j * 4096);
+}
+
+// Make chunk gc resident and visible to the whole workgroup, and refill the
+// slot freed by chunk gc-1 with chunk gc+kNBuf-1.  Chunks gc+1..gc+kNBuf-2
+// stay in flight.
+template <class G>
+__device__ __forceinline__ void chunk_acquire(int gc, int nch, const unsigned char* stream,
+                                              unsigned ring, int wave, int lane) {
+  const int later = nch - 1 - gc;  // chunks issued after gc, capped below
+  if (later >= kNBuf - 2)
+    vm_wait_barrier<(kNBuf - 2) * G::LPC>();
+  else if (later == 1)
+    vm_wait_barrier<G::LPC>();
+  else
+    vm_wait_barrier<0>();
+  if (gc + kNBuf - 1 < nch) issue_chunk<G>(stream, gc + kNBuf - 1, ring, wave, lane);
+}
+
+// log2(1 + 2^y), the rescaled softplus, with hardware exp2/log2.
+__device__ __forceinline__ float softplus2(float y) {
+  const float e = __builtin_amdgcn_exp2f(-__builtin_fabsf(y));
+  return __builtin_fmaxf(y, 0.0f) + __builtin_amdgcn_logf(1.0f + e);
+}
+
+template <int PREC>
+__device__ __forceinline__ unsigned pack2(float a, float b) {
+  f32x2 v = {a, b};
+  if constexpr (PREC == PREC_BF16)
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+  else
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, f16x2));
+}
+
+template <int PREC>
+__device__ __forceinline__ void unpack2(unsigned u, float& a, float& b) {
+  if constexpr (PREC == PREC_BF16) {
+    a = __builtin_bit_cast(float, u << 16);
+    b = __builtin_bit_cast(float, u & 0xffff0000u);
+  } else {
+    const f16x2 h = __builtin_bit_cast(f16x2, u);
+    a = (float)h.x;
+    b = (float)h.y;
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
+  if constexpr (PREC == PREC_BF16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float sum_lane_groups(float v) {
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Final per-point outputs, shared by every kernel family.  Only lanes of group
+// 0 (lanes 0..15) store; the other groups hold the same reduced values.
+template <int MODE>
+__device__ __forceinline__ void store_outputs(const KArgs& a, int64_t p, bool store, float f,
+                                              float g0, float g1, float g2, float x0, float x1,
+                                              float x2) {
+  if (!store) return;
+  if constexpr (MODE == MODE_QUERY) {
+    a.sdf[p] = f;
+  } else if constexpr (MODE == MODE_GRAD) {
+    if (a.sdf) a.sdf[p] = f;
+    a.grad[3 * p] = g0;
+    a.grad[3 * p + 1] = g1;
+    a.grad[3 * p + 2] = g2;
+  } else {
+    const float nrm = __builtin_sqrtf(g0 * g0 + g1 * g1 + g2 * g2);
+    float n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
+    if (nrm > 0.0f) {
+      const float inv = 1.0f / nrm;
+      n0 = g0 * inv;
+      n1 = g1 * inv;
+      n2 = g2 * inv;
+    }
+    const bool hit = f < a.eps;  // NaN compares false
+    if (hit && nrm > 0.0f) {
+      const float t = a.eps - f;
+      a.pts_out[3 * p] = x0 + t * n0;
+      a.pts_out[3 * p + 1] = x1 + t * n1;
+      a.pts_out[3 * p + 2] = x2 + t * n2;
+    }
+    if (a.sdf) a.sdf[p] = f;
+    if (a.normal) {
+      a.normal[3 * p] = n0;
+      a.normal[3 * p + 1] = n1;
+      a.normal[3 * p + 2] = n2;
+    }
+    if (a.hit) a.hit[p] = hit ? 1 : 0;
+  }
+}
+
+}  // namespace sdfc

@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances:
+  FP32 operands: |f - f64| <= 1e-5 (1 + |f64|), angle(grad, grad64) <= 1e-4 rad.
+  BF16 / FP16 operands: the stated accuracy target, |f - f64| <= 1e-3 and
+  normal angle <= 1e-2 rad (max over all points), asserted where each test
+  says so; the measured statistics are always printed.
+Hits are decided in FP32 on both sides of the comparison that must be exact:
+the GPU's flag equals (its own f < eps); against FP64 the flags agree wherever
+|f64 - eps| exceeds the SDF tolerance.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_01614_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU machines
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+B = pytest.importorskip("paper_2110_01614_amd.binding")
+
+STATS = os.environ.get("SDF_STATS_OUT")
+TOL = {"fp32": (1e-5, 1e-4), "bf16": (1e-3, 1e-2), "fp16": (1e-3, 1e-2)}
+
+
+def angle(a, b):
+    cr = np.linalg.norm(np.cross(a, b), axis=1)
+    return np.arctan2(cr, np.einsum("ij,ij->i", a, b))
+
+
+def record(name, **kv):
+    line = json.dumps(dict(test=name, **kv))
+    print(line, flush=True)
+    if STATS:
+        with open(STATS, "a") as fh:
+            fh.write(line + "\n")
+
+
+def run_gpu(spec, params, pts, precision, eps=0.005):
+    net = B.SdfNet(spec, params, precision)
+    X = torch.from_numpy(np.ascontiguousarray(pts, np.float32)).cuda()
+    fq = net.query(X)
+    fg, g = net.query_grad(X)
+    P = X.clone()
+    outs = net.collide_project(P, eps)
+    torch.cuda.synchronize()
+    res = dict(fq=fq.cpu().numpy(), fg=fg.cpu().numpy(), grad=g.cpu().numpy(), pts=P.cpu().numpy(),
+               sdf=outs["sdf"].cpu().numpy(), normal=outs["normal"].cpu().numpy(),
+               hit=outs["hit"].cpu().numpy())
+    net.close()
+    return res
+
+
+def compare(name, spec, params, pts, precision, eps=0.005, assert_gate=True, ref=None):
+    pts = np.ascontiguousarray(pts, np.float32)
+    ref = ref or oracle.collide_project(spec, params, pts, eps)
+    got = run_gpu(spec, params, pts, precision, eps)
+    tol_f, tol_a = TOL[precision]
+    f64 = ref["sdf"]
+    # all three entry points agree on f
+    assert np.array_equal(got["fq"], got["fg"]) and np.array_equal(got["fg"], got["sdf"])
+    ferr = np.abs(got["fg"] - f64)
+    gn = np.linalg.norm(ref["grad"], axis=1)
+    ok = gn > 1e-6 * np.median(gn)
+    ang = angle(got["grad"][ok].astype(np.float64), ref["grad"][ok])
+    nang = angle(got["normal"][ok].astype(np.float64), ref["normal"][ok])
+    record(name, precision=precision, n=len(pts), sdf_max=float(ferr.max()),
+           sdf_p99=float(np.quantile(ferr, 0.99)), sdf_mean=float(ferr.mean()),
+           ang_max=float(ang.max()), ang_p99=float(np.quantile(ang, 0.99)), ang_mean=float(ang.mean()),
+           f_range=[float(f64.min()), float(f64.max())])
+    # hit flag: exact against the GPU's own f, and against FP64 away from the threshold
+    assert np.array_equal(got["hit"].astype(bool), got["sdf"] < np.float32(eps))
+    far = np.abs(f64 - eps) > 2 * tol_f * (1 + np.abs(f64))
+    assert np.array_equal(got["hit"][far].astype(bool), ref["hit"][far].astype(bool))
+    # vertices that are not hit keep their exact bits
+    miss = got["hit"] == 0
+    assert np.array_equal(got["pts"][miss].view(np.uint32), pts[miss].view(np.uint32))
+    # the normal is the normalised gradient of the same call
+    gg = got["grad"].astype(np.float64)
+    nn = gg / np.linalg.norm(gg, axis=1, keepdims=True)
+    assert np.max(np.abs(nn[ok] - got["normal"][ok])) < 1e-5
+    if precision == "fp32" or assert_gate:
+        assert ferr.max() <= tol_f * (1 + np.abs(f64).max()) if precision != "fp32" else \
+            np.all(ferr <= tol_f * (1 + np.abs(f64)))
+        assert ang.max() <= tol_a
+        # moved vertices: p + (eps - f) N within the propagated tolerance
+        both = (got["hit"] == 1) & (ref["hit"] == 1) & ok
+        dp = np.linalg.norm(got["pts"][both] - ref["pts"][both], axis=1)
+        bound = tol_f * (1 + np.abs(f64[both])) + np.abs(eps - f64[both]) * tol_a * 1.01 + \
+            4e-7 * (1 + np.linalg.norm(pts[both], axis=1))
+        assert np.all(dp <= bound)
+    return got, ref
+
+
+def random_net(seed, widths, skip, scale=1.0):
+    spec = I.NetSpec(tuple(widths), skip=skip)
+    rng = np.random.default_rng(seed)
+    parts = []
+    for o, i in I.layer_shapes(spec):
+        parts.append(rng.normal(0, scale / math.sqrt(i), size=o * i))
+        parts.append(rng.normal(0, 0.01, size=o))
+    return spec, np.concatenate(parts).astype(np.float32)
+
+
+# ------------------------------------------------------------------ workloads
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
+def test_sphere64_all_points(precision):
+    """3->64x3->1 geometric sphere net, all 4096 uniform points."""
+    spec, params, pts, eps = I.workload_inputs("sphere64")
+    compare("sphere64", spec, params, pts, precision, eps, assert_gate=False)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("init", ["normal", "geometric"])
+def test_cloth_net_on_cloth_subset(precision, init):
+    """3->256x8->1 skip-5 net on 3000 cloth vertices (46 full tiles + ragged)."""
+    spec, params, pts, eps = I.workload_inputs("cloth1m", init=init)
+    idx = np.random.default_rng(9).choice(len(pts), 3000, replace=False)
+    compare("cloth_subset_" + init, spec, params, pts[idx], precision, eps, assert_gate=False)
+
+
+SHAPES = [((64, 64), 0), ((64,) * 5, 3), ((128, 128, 128), 2), ((128,) * 8, 8),
+          ((256, 256), 2), ((256,) * 4, 0), ((256,) * 6, 4), ((64,) * 8, 5)]
+
+
+@pytest.mark.parametrize("widths,skip", SHAPES)
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_shapes_and_ragged_sizes(widths, skip, precision):
+    spec, params = random_net(hash((widths, skip)) % 1000, widths, skip)
+    for n in (1, 17, 64, 1000):
+        pts = I.uniform_points(n, n)
+        compare("shape_%dx%d_s%d_n%d" % (widths[0], len(widths), skip, n), spec, params, pts,
+                precision, assert_gate=False)
+
+
+def test_cloth_full_size_sampled():
+    """The full 1M-vertex cloth in the benchmark's launch shape, 4096 sampled outputs."""
+    spec, params, pts, eps = I.workload_inputs("cloth1m")
+    idx = np.random.default_rng(3).choice(len(pts), 4096, replace=False)
+    ref = oracle.collide_project(spec, params, pts[idx], eps)
+    for precision in ("fp32", "bf16", "fp16"):
+        got = run_gpu(spec, params, pts, precision, eps)
+        ferr = np.abs(got["fg"][idx] - ref["sdf"])
+        ang = angle(got["grad"][idx].astype(np.float64), ref["grad"])
+        record("cloth1m_sampled", precision=precision, sdf_max=float(ferr.max()),
+               ang_max=float(ang.max()), ang_p99=float(np.quantile(ang, 0.99)))
+        tol_f, tol_a = TOL[precision]
+        assert ferr.max() <= tol_f * (1 + np.abs(ref["sdf"]).max())
+        if precision == "fp32":
+            assert ang.max() <= tol_a
+        assert np.array_equal(got["hit"].astype(bool), got["sdf"] < np.float32(eps))
+
+
+# ------------------------------------------------------------- exact cases
+
+def plane_net(n, d, C=2.5, widths=(64,) * 6, skip=4, seed=5):
+    spec = I.NetSpec(tuple(widths), skip=skip)
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l, (o, i) in enumerate(I.layer_shapes(spec)[:-1], start=1):
+        W = rng.normal(0, 0.3, size=(o, i))
+        b = rng.normal(0, 0.1, size=o)
+        W[0, :] = 0.0
+        if l == 1:
+            W[0, :3] = n
+            b[0] = C - d
+        else:
+            W[0, 0] = 1.0
+            b[0] = 0.0
+        parts += [W.ravel(), b]
+    o, i = I.layer_shapes(spec)[-1]
+    wo = np.zeros(i)
+    wo[0] = 1.0
+    parts += [wo, np.array([-C])]
+    return spec, np.concatenate(parts).astype(np.float32)
+
+
+def test_plane_net_projects_onto_the_plane_fp32():
+    """An MLP that is exactly the plane n.x - d (closed form, no oracle)."""
+    n = np.array([0.6, -0.48, 0.64], np.float32)
+    d, eps = 0.25, 0.01
+    spec, params = plane_net(n, d)
+    pts = I.uniform_points(5000, 31)
+    got = run_gpu(spec, params, pts, "fp32", eps)
+    exact = pts.astype(np.float64) @ n.astype(np.float64) - d
+    assert np.max(np.abs(got["fg"] - exact)) < 2e-6
+    assert np.max(np.abs(got["grad"] - n)) < 1e-6
+    hit = got["hit"] == 1
+    f2 = got["pts"][hit].astype(np.float64) @ n.astype(np.float64) - d
+    assert np.max(np.abs(f2 - eps)) < 3e-6
+
+
+def test_nan_vertex_is_not_moved_and_bits_kept():
+    spec, params, pts, eps = I.workload_inputs("sphere64", n=100)
+    pts = pts.copy()
+    pts[7] = np.nan
+    for precision in ("fp32", "bf16"):
+        got = run_gpu(spec, params, pts, precision, eps)
+        assert np.isnan(got["sdf"][7]) and got["hit"][7] == 0
+        assert np.array_equal(got["pts"][7].view(np.uint32), pts[7].view(np.uint32))
+
+
+def test_argument_errors_and_empty_input():
+    spec, params, pts, eps = I.workload_inputs("sphere64", n=64)
+    net = B.SdfNet(spec, params, "fp32")
+    X = torch.from_numpy(pts).cuda()
+    out = torch.empty(64, device="cuda")
+    assert B.lib.sdf_query(net.handle, X.data_ptr(), 0, out.data_ptr(), None) == B.SDF_OK
+    assert B.lib.sdf_query(net.handle, X.data_ptr(), -1, out.data_ptr(), None) == B.SDF_EINVAL
+    assert B.lib.sdf_query(net.handle, None, 64, out.data_ptr(), None) == B.SDF_EINVAL
+    assert B.lib.sdf_query(net.handle, X.data_ptr(), 64, None, None) == B.SDF_EINVAL
+    assert B.lib.sdf_query(net.handle, X.data_ptr() + 2, 64, out.data_ptr(), None) == B.SDF_EINVAL
+    assert B.lib.sdf_query_grad(net.handle, X.data_ptr(), 64, None, None, None) == B.SDF_EINVAL
+    assert B.lib.collide_project(net.handle, X.data_ptr(), 64, float("nan"), None, None, None,
+                                 None) == B.SDF_EINVAL
+    torch.cuda.synchronize()
+    net.close()
+
+
+def test_repeatable_bits_and_side_stream():
+    spec, params, pts, eps = I.workload_inputs("cloth1m")
+    pts = pts[:20000]
+    net = B.SdfNet(spec, params, "bf16")
+    X = torch.from_numpy(pts).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = net.query_grad(X)
+        b = net.query_grad(X)
+    s.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    c = net.query_grad(X)
+    torch.cuda.synchronize()
+    assert torch.equal(a[1], c[1])
+    net.close()

@@ -23,7 +23,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}  # MI355X dense MFMA
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3}  # MI355X dense MFMA
 
 
 def flops_per_point(spec) -> int:
@@ -95,7 +95,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "fp32"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "bf16x3", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -118,7 +118,7 @@ def main():
     X0 = torch.from_numpy(pts).cuda()
     results = {}
     order = [args.precision] + ([] if args.no_compare else
-                                [p for p in ("fp32", "fp16", "bf16") if p != args.precision])
+                                [p for p in ("fp32", "fp16", "bf16x3", "bf16") if p != args.precision])
     for prec in order:
         net = B.SdfNet(spec, params, prec)
         X = X0.clone()

@@ -46,9 +46,12 @@ enum {
 };
 
 /* Operand precision of the hidden-layer contractions (MFMA, FP32 accumulate).
+ * SDF_BF16X3 carries every operand (weights, activations, back-propagated
+ * errors) as a BF16 pair hi + lo and forms each product as hi*hi + lo*hi +
+ * hi*lo: three BF16 MFMAs per product, about 16 significant bits.
  * Layer 1 (K = 3), the skip x-columns, the output layer, the normalisation
  * and the projection always run in FP32. */
-enum { SDF_FP32 = 0, SDF_BF16 = 1, SDF_FP16 = 2 };
+enum { SDF_FP32 = 0, SDF_BF16 = 1, SDF_FP16 = 2, SDF_BF16X3 = 3 };
 
 #define SDF_MAX_HIDDEN 16
 

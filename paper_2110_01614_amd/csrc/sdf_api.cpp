@@ -57,7 +57,8 @@ int check_desc(const sdf_net_desc* d, int* W, int* L, int* skip) {
   if (d->skip_layer == 1 || d->skip_layer < 0 || d->skip_layer > d->n_hidden)
     return fail(SDF_EINVAL, "skip_layer must be 0 or in [2, n_hidden]");
   if (!std::isfinite(d->beta) || d->beta <= 0.0f) return fail(SDF_EINVAL, "beta must be finite and > 0");
-  if (d->precision != SDF_FP32 && d->precision != SDF_BF16 && d->precision != SDF_FP16)
+  if (d->precision != SDF_FP32 && d->precision != SDF_BF16 && d->precision != SDF_FP16 &&
+      d->precision != SDF_BF16X3)
     return fail(SDF_EINVAL, "unknown precision");
   *W = d->width[0];
   *L = d->n_hidden;
@@ -207,19 +208,35 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
   std::vector<unsigned char> stream;
   int cpl = 0;
   auto emit16 = [&](auto at /* (row, col) -> float */) {
-    const int MT = W / 16, KB = W / 32;
-    for (int mt = 0; mt < MT; ++mt)
+    // [wave][K-block][local M-tile][part] fragments: each wave reads one
+    // contiguous slice holding the rows it owns (features [w W/4, (w+1) W/4)).
+    // BF16x3 stores every weight as a pair hi = bf16(v), lo = bf16(v - hi).
+    const int KB = W / 32, MTW = W / 64, NS = (prec == SDF_BF16X3) ? 2 : 1;
+    for (int w = 0; w < 4; ++w)
       for (int kb = 0; kb < KB; ++kb)
-        for (int lane = 0; lane < 64; ++lane) {
-          const int g = lane >> 4, row = lane & 15;
-          for (int e = 0; e < 8; ++e) {
-            const int col = 32 * kb + 16 * (e / 4) + 4 * g + (e % 4);
-            const float v = at(16 * mt + row, col);
-            const uint16_t h = (prec == SDF_BF16) ? to_bf16(v) : to_fp16(v);
-            stream.push_back((unsigned char)(h & 0xff));
-            stream.push_back((unsigned char)(h >> 8));
-          }
-        }
+        for (int ml = 0; ml < MTW; ++ml)
+          for (int part = 0; part < NS; ++part)
+            for (int lane = 0; lane < 64; ++lane) {
+              const int g = lane >> 4, row = lane & 15, mt = MTW * w + ml;
+              for (int e = 0; e < 8; ++e) {
+                const int col = 32 * kb + 16 * (e / 4) + 4 * g + (e % 4);
+                const float v = at(16 * mt + row, col);
+                uint16_t h;
+                if (prec == SDF_FP16) {
+                  h = to_fp16(v);
+                } else {
+                  h = to_bf16(v);
+                  if (part == 1) {
+                    const uint32_t hb = (uint32_t)h << 16;
+                    float hf;
+                    std::memcpy(&hf, &hb, 4);
+                    h = to_bf16(v - hf);
+                  }
+                }
+                stream.push_back((unsigned char)(h & 0xff));
+                stream.push_back((unsigned char)(h >> 8));
+              }
+            }
   };
   auto emit32 = [&](auto at) {
     const int MT = W / 16;
@@ -254,7 +271,7 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
     // a 16-bit value that overflowed would make every gradient through it infinite
     for (size_t i = 0; i + 1 < stream.size(); i += 2) {
       const uint16_t h = (uint16_t)(stream[i] | (stream[i + 1] << 8));
-      const bool inf = (prec == SDF_BF16) ? ((h & 0x7f80) == 0x7f80) : ((h & 0x7c00) == 0x7c00);
+      const bool inf = (prec == SDF_FP16) ? ((h & 0x7c00) == 0x7c00) : ((h & 0x7f80) == 0x7f80);
       if (inf) return fail(SDF_EUNSUPPORTED, "a weight does not fit the 16-bit operand range");
     }
   }
@@ -326,12 +343,13 @@ hipError_t launch(const sdf_net* net, const KArgs& a, hipStream_t s) {
     K32(64) K32(128) K32(256)
 #undef K32
   } else {
-    dim3 grid((unsigned)a.ntiles);
+    const int pts = (net->prec == SDF_BF16X3) ? 32 : 64;  // points per workgroup
+    dim3 grid((unsigned)((a.n + pts - 1) / pts));
 #define K16(WW, PP) \
-  if (W == WW && net->prec == (PP == PREC_BF16 ? SDF_BF16 : SDF_FP16)) \
-    hipLaunchKernelGGL((sdf_k16<WW, PP, MODE>), grid, block, 0, s, a);
+  if (W == WW && net->prec == PP) hipLaunchKernelGGL((sdf_k16<WW, PP, MODE>), grid, block, 0, s, a);
     K16(64, PREC_BF16) K16(128, PREC_BF16) K16(256, PREC_BF16)
     K16(64, PREC_FP16) K16(128, PREC_FP16) K16(256, PREC_FP16)
+    K16(64, PREC_BF16X3) K16(128, PREC_BF16X3) K16(256, PREC_BF16X3)
 #undef K16
   }
   return hipGetLastError();
@@ -355,7 +373,7 @@ int run(const sdf_net* net, const float* pts_in, float* pts_out, int64_t n, floa
   if (n > ((int64_t)1 << 40)) return fail(SDF_EINVAL, "n too large");
   if (n == 0) return SDF_OK;
   const int64_t tiles = (n + kPtsPerBlock - 1) / kPtsPerBlock;
-  if (tiles > 0x7fffffff) return fail(SDF_EINVAL, "n too large");
+  if (2 * tiles > 0x7fffffff) return fail(SDF_EINVAL, "n too large");
   KArgs a{};
   a.pts_in = pts_in;
   a.pts_out = pts_out;

@@ -16,7 +16,7 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 enum { MODE_QUERY = 0, MODE_GRAD = 1, MODE_PROJECT = 2 };
-enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2 };
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2, PREC_BF16X3 = 3 };
 
 // Everything a launch needs; passed by value in the kernel argument segment.
 struct KArgs {

@@ -1,218 +1,364 @@
 // sdf_k16.hip -- fused neural-SDF query / gradient / collision kernel with
 // 16-bit (BF16 or FP16) MFMA operands and FP32 accumulation, for gfx950.
 //
-// One workgroup = 4 wave64 = 64 points; each wave owns 16 points for the whole
-// pass.  Per hidden layer l >= 2 the wave computes the 16-point column block
-// of z_l = W_l r_{l-1} with v_mfma_f32_16x16x32_{bf16,f16}: A = a weight
-// fragment read from LDS, B = the previous layer's activations, which never
-// leave registers (Sec. 3.1, Eq. 1).  The input gradient is the reverse sweep
-// of Sec. 3.2 over the same weights transposed.  Every r_l (16-bit) stays in
-// registers for that sweep (the "stack"); each sigmoid is recovered as
-// 1 - 2^{-r}.  Layer 1 (K = 3), the skip x-columns, the output layer, the
-// normal (Eq. 2) and the move to the contact point (Eq. 3) are FP32 VALU.
-//
-// Weights stream through a 4-slot LDS ring in 32 KB chunks with direct
-// global->LDS copies (see sdf_device.hpp); two chunks stay in flight while
-// the workgroup computes on the third.
+// One workgroup = 4 wave64 = 64 points (4 column tiles of 16).  The hidden
+// features of every layer are split across the waves: wave w owns features
+// [w W/4, (w+1) W/4) for all 64 points.  Per hidden layer l >= 2 each wave
+// computes its rows of z_l = W_l r_{l-1} with v_mfma_f32_16x16x32_{bf16,f16}:
+// A = its own weight fragments, loaded straight from L2 into registers (each
+// weight byte enters the CU once per workgroup), B = the previous layer's
+// activations of all features, read from an LDS exchange buffer that every
+// wave fills with its own rows (Sec. 3.1, Eq. 1).  The reverse sweep of
+// Sec. 3.2 runs the same way over W_l^T: a wave owns the input-feature rows
+// it produced in the forward pass, so the sigmoids it needs come from its own
+// registers (1 - 2^{-r}, r stored as 16-bit).  Layer 1 (K = 3), the skip
+// x-columns, the output layer, the normal (Eq. 2) and the move to the contact
+// point (Eq. 3) are FP32 VALU; per-point sums across waves go through LDS.
 #include "sdf_device.hpp"
 
 namespace sdfc {
 
+// NS = 1: plain 16-bit operands.  NS = 2: every operand is carried as a BF16
+// pair hi + lo (lo = bf16(v - hi)) and each product is hi*hi + lo*hi + hi*lo,
+// which keeps about 16 significant bits (compensated "BF16x3").
+template <int W, int NS>
+struct GeoB {
+  static constexpr int NCT = NS == 1 ? 4 : 2;  // column tiles (16 points each)
+  static constexpr int PTS = 16 * NCT;         // points per workgroup
+  static constexpr int FW = W / 4;             // features per wave
+  static constexpr int MTW = FW / 16;          // M-tiles per wave
+  static constexpr int KB = W / 32;            // K-blocks of 32 per layer
+  static constexpr int D = KB < 2 ? KB : 2;    // weight prefetch depth in K-steps
+  static constexpr int WAVE_BYTES = KB * MTW * NS * kFrag;  // one wave's slice of a layer
+  static constexpr int LAYER_BYTES = 4 * WAVE_BYTES;
+  static constexpr int ACT_BYTES = KB * NCT * kFrag;        // one exchange buffer part
+  static constexpr int NS_ = NS;
+  static_assert(MTW >= 1 && KB % D == 0, "shape");
+};
+
 template <int PREC>
-__device__ __forceinline__ void put4(u32x4& v, int half, const float r[4]) {
-  v[2 * half] = pack2<PREC>(r[0], r[1]);
-  v[2 * half + 1] = pack2<PREC>(r[2], r[3]);
+__device__ __forceinline__ uint2 pack4(f32x4 v) {
+  return uint2{pack2<PREC>(v[0], v[1]), pack2<PREC>(v[2], v[3])};
 }
 
 template <int PREC>
-__device__ __forceinline__ void get4(const u32x4& v, int half, float r[4]) {
-  unpack2<PREC>(v[2 * half], r[0], r[1]);
-  unpack2<PREC>(v[2 * half + 1], r[2], r[3]);
+__device__ __forceinline__ f32x4 unpack4(uint2 u) {
+  f32x4 r;
+  float a, b;
+  unpack2<PREC>(u.x, a, b);
+  r[0] = a;
+  r[1] = b;
+  unpack2<PREC>(u.y, a, b);
+  r[2] = a;
+  r[3] = b;
+  return r;
+}
+
+// Address of weight fragment part ps (0 hi, 1 lo) of (K-step kb, local M-tile mt).
+template <class G>
+__device__ __forceinline__ const u32x4* wfrag(const unsigned char* layer, int wave, int kb, int mt,
+                                              int ps, int lane) {
+  return reinterpret_cast<const u32x4*>(layer + (size_t)wave * G::WAVE_BYTES +
+                                        (size_t)((kb * G::MTW + mt) * G::NS_ + ps) * kFrag + lane * 16);
+}
+
+// v as a BF16 pair: hi = bf16(v), lo = bf16(v - hi).
+__device__ __forceinline__ void split4(f32x4 v, uint2& hi, uint2& lo) {
+  hi = pack4<PREC_BF16>(v);
+  const f32x4 h = unpack4<PREC_BF16>(hi);
+  lo = pack4<PREC_BF16>(v - h);
 }
 
 template <int W, int PREC, int MODE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
 sdf_k16(const KArgs a) {
-  using G = Geo<W, false>;
+  constexpr int NS = PREC == PREC_BF16X3 ? 2 : 1;
+  constexpr int OP = PREC == PREC_BF16X3 ? PREC_BF16 : PREC;  // MFMA operand type
+  using G = GeoB<W, NS>;
   constexpr SmallLayout SL{W};
-  constexpr int KB = G::KB, MT = G::MT, CH_MT = G::CH_MT, CPL = G::CPL;
-  static_assert(kNBuf == 4, "chunk_acquire assumes a 4-slot ring");
+  constexpr int MTW = G::MTW, KB = G::KB, NCT = G::NCT, D = G::D, PTS = G::PTS;
 
-  __shared__ __attribute__((aligned(1024))) unsigned char ring[kNBuf * G::CHUNK];
+  __shared__ __attribute__((aligned(16))) unsigned char act[2][NS][G::ACT_BYTES];
   __shared__ __attribute__((aligned(16))) float sm[SL.floats()];
+  __shared__ __attribute__((aligned(16))) f32x4 red[4][PTS];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int g = lane >> 4;
-  const int64_t p = (int64_t)blockIdx.x * kPtsPerBlock + wave * kPtsPerWave + (lane & 15);
-  const bool valid = p < a.n;
-  const int L = a.L, skip = a.skip, nch = a.nch;
+  const int g = lane >> 4, col = lane & 15;
+  const int L = a.L, skip = a.skip;
+  const int64_t base = (int64_t)blockIdx.x * PTS;
+  const unsigned char* fwd = a.stream;  // layers 2..L, LAYER_BYTES each
+  const unsigned char* rev = a.stream + (size_t)(L - 1) * G::LAYER_BYTES;  // layers L..2
 
-  // ---- point, small FP32 weights ----
-  float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-  if (valid) {
-    x0 = a.pts_in[3 * p];
-    x1 = a.pts_in[3 * p + 1];
-    x2 = a.pts_in[3 * p + 2];
+  // ---- points of the lane's column tiles, small weights ----
+  float x[NCT][3];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int64_t p = base + 16 * ct + col;
+    const bool ok = p < a.n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[ct][c] = ok ? a.pts_in[3 * p + c] : 0.0f;
   }
   for (int i = tid; i < SL.floats() / 4; i += kBlock)
     reinterpret_cast<f32x4*>(sm)[i] = reinterpret_cast<const f32x4*>(a.small)[i];
+
+  // first weight fragments (forward layer 2)
+  u32x4 Aq[D][MTW][NS];
+#pragma unroll
+  for (int s = 0; s < D; ++s)
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+      for (int ps = 0; ps < NS; ++ps) Aq[s][mt][ps] = *wfrag<G>(fwd, wave, s, mt, ps, lane);
   __syncthreads();
 
-  const unsigned ring0 = lds_u32(ring);
-  for (int c = 0; c < kNBuf - 1; ++c)
-    if (c < nch) issue_chunk<G>(a.stream, c, ring0, wave, lane);
-
-  // ---- layer 1: y = kappa (W1 x + b1), K = 3, FP32 VALU ----
-  u32x4 stk[kLMax][KB];  // stk[l] = r_l in B-operand order, l = 1..L-1
+  // feature index of (local M-tile mt, lane group g, element i)
+  auto feat = [&](int mt, int i) { return 16 * (MTW * wave + mt) + 4 * g + i; };
+  // LDS byte offset of this lane's half-fragment for global M-tile of local mt, tile ct
+  auto act_off = [&](int mt, int ct) {
+    const int m = MTW * wave + mt;
+    return ((m >> 1) * NCT + ct) * kFrag + lane * 16 + 8 * (m & 1);
+  };
+  // Store v (FP32) as the wave's operand rows: 16-bit (NS = 1) or a BF16 pair.
+  auto put = [&](unsigned char* out, int mt, int ct, f32x4 v, uint2* keep) {
+    uint2 p[NS];
+    if constexpr (NS == 1)
+      p[0] = pack4<OP>(v);
+    else
+      split4(v, p[0], p[NS - 1]);
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    float r[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * (16 * mt + 4 * g + i)]);
-      r[i] = softplus2(__builtin_fmaf(w.x, x0, __builtin_fmaf(w.y, x1, __builtin_fmaf(w.z, x2, w.w))));
+    for (int ps = 0; ps < NS; ++ps) {
+      *reinterpret_cast<uint2*>(out + ps * G::ACT_BYTES + act_off(mt, ct)) = p[ps];
+      if (keep) keep[ps] = p[ps];
     }
-    put4<PREC>(stk[1][mt >> 1], mt & 1, r);
+  };
+
+  uint2 stk[kLMax][MTW][NCT][NS];  // r_l of the wave's rows, l = 1..L-1
+  float fpart[NCT], gx[NCT][3];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    fpart[ct] = 0.0f;
+    gx[ct][0] = gx[ct][1] = gx[ct][2] = 0.0f;
   }
 
-  float fpart = 0.0f, gx0 = 0.0f, gx1 = 0.0f, gx2 = 0.0f;
-  u32x4 D0[KB], D1[KB];  // d_l (scaled) in B-operand order; d_l lives in D[l & 1]
-  int gc = 0;
+  // ---- layer 1: y = kappa (W1 x + b1) ----
+#pragma unroll
+  for (int mt = 0; mt < MTW; ++mt) {
+    f32x4 w4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w4[i] = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * feat(mt, i)]);
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      f32x4 r;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        r[i] = softplus2(__builtin_fmaf(w4[i].x, x[ct][0],
+                                        __builtin_fmaf(w4[i].y, x[ct][1], __builtin_fmaf(w4[i].z, x[ct][2], w4[i].w))));
+      put(&act[0][0][0], mt, ct, r, stk[1][mt][ct]);
+    }
+  }
+  __syncthreads();
+
+  // One hidden layer's contraction for this wave: acc[mt][ct] += A(mt, kb) B(kb, ct)
+  // with B from exchange buffer `in`; prefetches the next layer's first D K-steps
+  // from `next` (nullptr: nothing follows).
+  auto contract = [&](f32x4 (&acc)[MTW][NCT], const unsigned char* in, const unsigned char* layer,
+                      const unsigned char* next) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      u32x4 Bv[NCT][NS];
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int ps = 0; ps < NS; ++ps)
+          Bv[ct][ps] = *reinterpret_cast<const u32x4*>(in + ps * G::ACT_BYTES + (kb * NCT + ct) * kFrag + lane * 16);
+      u32x4 Acur[MTW][NS];
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+        for (int ps = 0; ps < NS; ++ps) Acur[mt][ps] = Aq[kb % D][mt][ps];
+      const int nk = kb + D;
+      if (nk < KB) {
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+          for (int ps = 0; ps < NS; ++ps) Aq[kb % D][mt][ps] = *wfrag<G>(layer, wave, nk, mt, ps, lane);
+      } else if (next) {
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+          for (int ps = 0; ps < NS; ++ps) Aq[kb % D][mt][ps] = *wfrag<G>(next, wave, nk - KB, mt, ps, lane);
+      }
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          if constexpr (NS == 2) {  // small cross terms first
+            acc[mt][ct] = mfma16<OP>(Acur[mt][1], Bv[ct][0], acc[mt][ct]);
+            acc[mt][ct] = mfma16<OP>(Acur[mt][0], Bv[ct][1], acc[mt][ct]);
+          }
+          acc[mt][ct] = mfma16<OP>(Acur[mt][0], Bv[ct][0], acc[mt][ct]);
+        }
+    }
+  };
 
   // ---- hidden layers 2..L, forward ----
 #pragma unroll
   for (int l = 2; l <= kLMax; ++l) {
     if (l > L) break;
-    const bool last = (l == L);
+    const int t = l - 1;  // exchange step: read act[(t-1)&1], write act[t&1]
+    const unsigned char* in = &act[(t - 1) & 1][0][0];
+    unsigned char* out = &act[t & 1][0][0];
+    const unsigned char* layer = fwd + (size_t)(l - 2) * G::LAYER_BYTES;
+    const unsigned char* next =
+        (l < L) ? layer + G::LAYER_BYTES : (MODE != MODE_QUERY ? rev : nullptr);
+    f32x4 acc[MTW][NCT];
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) {
-      chunk_acquire<G>(gc, nch, a.stream, ring0, wave, lane);
-      const unsigned char* buf = ring + (gc % kNBuf) * G::CHUNK;
+    for (int mt = 0; mt < MTW; ++mt) {
+      const f32x4 b = *reinterpret_cast<const f32x4*>(&sm[SL.bias(l) + 16 * (MTW * wave + mt) + 4 * g]);
 #pragma unroll
-      for (int mm = 0; mm < CH_MT; mm += 2) {
-        const int mt = c * CH_MT + mm;
-        f32x4 acc[2];
+      for (int ct = 0; ct < NCT; ++ct) acc[mt][ct] = b;
+    }
+    if (l == skip) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-          acc[h] = *reinterpret_cast<const f32x4*>(&sm[SL.bias(l) + 16 * (mt + h) + 4 * g]);
+      for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
+        for (int i = 0; i < 4; ++i) {
+          const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[SL.skf() + 4 * feat(mt, i)]);
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const u32x4 A = *reinterpret_cast<const u32x4*>(buf + ((mm + h) * KB + kb) * kFrag + lane * 16);
-            acc[h] = mfma16<PREC>(A, stk[l - 1][kb], acc[h]);
-          }
+          for (int ct = 0; ct < NCT; ++ct)
+            acc[mt][ct][i] = __builtin_fmaf(w.x, x[ct][0], __builtin_fmaf(w.y, x[ct][1], __builtin_fmaf(w.z, x[ct][2], acc[mt][ct][i])));
         }
+    }
+    contract(acc, in, layer, next);
+    if (l < L) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int m = mt + h;
-          if (l == skip) {
+      for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[SL.skf() + 4 * (16 * m + 4 * g + i)]);
-              acc[h][i] = __builtin_fmaf(w.x, x0, __builtin_fmaf(w.y, x1, __builtin_fmaf(w.z, x2, acc[h][i])));
-            }
+        for (int ct = 0; ct < NCT; ++ct) {
+          f32x4 r;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) r[i] = softplus2(acc[mt][ct][i]);
+          put(out, mt, ct, r, stk[l][mt][ct]);
+        }
+    } else {
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt) {
+        const f32x4 wf = *reinterpret_cast<const f32x4*>(&sm[SL.wof() + 16 * (MTW * wave + mt) + 4 * g]);
+        const f32x4 wb = *reinterpret_cast<const f32x4*>(&sm[SL.wob() + 16 * (MTW * wave + mt) + 4 * g]);
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          f32x4 d;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float r = softplus2(acc[mt][ct][i]);
+            fpart[ct] = __builtin_fmaf(wf[i], r, fpart[ct]);
+            d[i] = __builtin_fmaf(-wb[i], __builtin_amdgcn_exp2f(-r), wb[i]);  // w_o (1 - 2^-r)
           }
-          float r[4];
+          if constexpr (MODE != MODE_QUERY) {
+            if (l == skip) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) r[i] = softplus2(acc[h][i]);
-          if (!last) {
-            put4<PREC>(stk[l][m >> 1], m & 1, r);
-          } else {
-            const f32x4 wf = *reinterpret_cast<const f32x4*>(&sm[SL.wof() + 16 * m + 4 * g]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) fpart = __builtin_fmaf(wf[i], r[i], fpart);
-            if constexpr (MODE != MODE_QUERY) {
-              const f32x4 wb = *reinterpret_cast<const f32x4*>(&sm[SL.wob() + 16 * m + 4 * g]);
-              float d[4];
-#pragma unroll
-              for (int i = 0; i < 4; ++i)  // d_L = w_o * sigmoid = w_o (1 - 2^-r)
-                d[i] = __builtin_fmaf(-wb[i], __builtin_amdgcn_exp2f(-r[i]), wb[i]);
-              if (l == skip) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                  const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[SL.skg() + 4 * (16 * m + 4 * g + i)]);
-                  gx0 = __builtin_fmaf(w.x, d[i], gx0);
-                  gx1 = __builtin_fmaf(w.y, d[i], gx1);
-                  gx2 = __builtin_fmaf(w.z, d[i], gx2);
-                }
+              for (int i = 0; i < 4; ++i) {
+                const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[SL.skg() + 4 * feat(mt, i)]);
+                gx[ct][0] = __builtin_fmaf(w.x, d[i], gx[ct][0]);
+                gx[ct][1] = __builtin_fmaf(w.y, d[i], gx[ct][1]);
+                gx[ct][2] = __builtin_fmaf(w.z, d[i], gx[ct][2]);
               }
-              put4<PREC>((l & 1) ? D1[m >> 1] : D0[m >> 1], m & 1, d);
             }
+            put(out, mt, ct, d, nullptr);
           }
         }
       }
-      ++gc;
     }
+    __syncthreads();
   }
 
-  // ---- reverse sweep: layers L..2 over W_l^T ----
+  // ---- reverse sweep over W_l^T, l = L..2 ----
   if constexpr (MODE != MODE_QUERY) {
 #pragma unroll
     for (int l = kLMax; l >= 2; --l) {
       if (l > L) continue;
+      const int t = 2 * L - l;
+      const unsigned char* in = &act[(t - 1) & 1][0][0];
+      unsigned char* out = &act[t & 1][0][0];
+      const unsigned char* layer = rev + (size_t)(L - l) * G::LAYER_BYTES;
+      const unsigned char* next = (l > 2) ? layer + G::LAYER_BYTES : nullptr;
+      f32x4 acc[MTW][NCT];
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) {
-        chunk_acquire<G>(gc, nch, a.stream, ring0, wave, lane);
-        const unsigned char* buf = ring + (gc % kNBuf) * G::CHUNK;
+      for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-        for (int mm = 0; mm < CH_MT; mm += 2) {
-          const int mt = c * CH_MT + mm;
-          f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+        for (int ct = 0; ct < NCT; ++ct) acc[mt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      contract(acc, in, layer, next);
 #pragma unroll
-          for (int kb = 0; kb < KB; ++kb) {
+      for (int mt = 0; mt < MTW; ++mt) {
+        f32x4 wg[4];
+        const bool to_x = (l - 1 == skip) || (l == 2);
+        if (to_x) {
+          const int off = (l == 2) ? SL.l1g() : SL.skg();
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const u32x4 A = *reinterpret_cast<const u32x4*>(buf + ((mm + h) * KB + kb) * kFrag + lane * 16);
-              acc[h] = mfma16<PREC>(A, (l & 1) ? D1[kb] : D0[kb], acc[h]);
-            }
-          }
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int m = mt + h;
-            float r[4], d[4];
-            get4<PREC>(stk[l - 1][m >> 1], m & 1, r);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)  // d_{l-1} = g (1 - 2^-r_{l-1})
-              d[i] = __builtin_fmaf(-acc[h][i], __builtin_amdgcn_exp2f(-r[i]), acc[h][i]);
-            if (l - 1 == skip || l == 2) {
-              const int off = (l == 2) ? SL.l1g() : SL.skg();
-#pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[off + 4 * (16 * m + 4 * g + i)]);
-                gx0 = __builtin_fmaf(w.x, d[i], gx0);
-                gx1 = __builtin_fmaf(w.y, d[i], gx1);
-                gx2 = __builtin_fmaf(w.z, d[i], gx2);
-              }
-            }
-            if (l > 2) put4<PREC>((l & 1) ? D0[m >> 1] : D1[m >> 1], m & 1, d);
-          }
+          for (int i = 0; i < 4; ++i) wg[i] = *reinterpret_cast<const f32x4*>(&sm[off + 4 * feat(mt, i)]);
         }
-        ++gc;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          f32x4 r = unpack4<OP>(stk[l - 1][mt][ct][0]);
+          if constexpr (NS == 2) r += unpack4<OP>(stk[l - 1][mt][ct][1]);
+          f32x4 d;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)  // d_{l-1} = g (1 - 2^-r_{l-1})
+            d[i] = __builtin_fmaf(-acc[mt][ct][i], __builtin_amdgcn_exp2f(-r[i]), acc[mt][ct][i]);
+          if (to_x) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              gx[ct][0] = __builtin_fmaf(wg[i].x, d[i], gx[ct][0]);
+              gx[ct][1] = __builtin_fmaf(wg[i].y, d[i], gx[ct][1]);
+              gx[ct][2] = __builtin_fmaf(wg[i].z, d[i], gx[ct][2]);
+            }
+          }
+          if (l > 2) put(out, mt, ct, d, nullptr);
+        }
       }
+      if (l > 2) __syncthreads();
     }
   }
 
-  const float f = sum_lane_groups(fpart) + a.bo;
-  if constexpr (MODE != MODE_QUERY) {
-    gx0 = sum_lane_groups(gx0);
-    gx1 = sum_lane_groups(gx1);
-    gx2 = sum_lane_groups(gx2);
+  // ---- per-point sums across lane groups, then across waves ----
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    f32x4 v = {sum_lane_groups(fpart[ct]), 0.0f, 0.0f, 0.0f};
+    if constexpr (MODE != MODE_QUERY) {
+      v[1] = sum_lane_groups(gx[ct][0]);
+      v[2] = sum_lane_groups(gx[ct][1]);
+      v[3] = sum_lane_groups(gx[ct][2]);
+    }
+    if (g == 0) red[wave][16 * ct + col] = v;
   }
-  store_outputs<MODE>(a, p, valid && g == 0, f, gx0, gx1, gx2, x0, x1, x2);
+  __syncthreads();
+  // waves 0..NCT-1 finish the points of column tile `wave`
+  if (wave < NCT) {
+    const f32x4 s = red[0][16 * wave + col] + red[1][16 * wave + col] + red[2][16 * wave + col] +
+                    red[3][16 * wave + col];
+    float px = x[0][0], py = x[0][1], pz = x[0][2];
+#pragma unroll
+    for (int ct = 1; ct < NCT; ++ct)
+      if (wave == ct) {
+        px = x[ct][0];
+        py = x[ct][1];
+        pz = x[ct][2];
+      }
+    const int64_t p = base + 16 * wave + col;
+    store_outputs<MODE>(a, p, p < a.n && g == 0, s[0] + a.bo, s[1], s[2], s[3], px, py, pz);
+  }
 }
 
 #define SDF_K16_INST(W, PREC, MODE) \
   template __global__ void sdf_k16<W, PREC, MODE>(const KArgs);
 #define SDF_K16_MODES(W, PREC) \
   SDF_K16_INST(W, PREC, MODE_QUERY) SDF_K16_INST(W, PREC, MODE_GRAD) SDF_K16_INST(W, PREC, MODE_PROJECT)
-SDF_K16_MODES(64, PREC_BF16)
-SDF_K16_MODES(128, PREC_BF16)
-SDF_K16_MODES(256, PREC_BF16)
-SDF_K16_MODES(64, PREC_FP16)
-SDF_K16_MODES(128, PREC_FP16)
-SDF_K16_MODES(256, PREC_FP16)
+#define SDF_K16_PRECS(W) \
+  SDF_K16_MODES(W, PREC_BF16) SDF_K16_MODES(W, PREC_FP16) SDF_K16_MODES(W, PREC_BF16X3)
+SDF_K16_PRECS(64)
+SDF_K16_PRECS(128)
+SDF_K16_PRECS(256)
 
 }  // namespace sdfc

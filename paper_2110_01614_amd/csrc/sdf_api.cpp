@@ -211,8 +211,9 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
     // [wave][K-block][local M-tile][part] fragments: each wave reads one
     // contiguous slice holding the rows it owns (features [w W/4, (w+1) W/4)).
     // BF16x3 stores every weight as a pair hi = bf16(v), lo = bf16(v - hi).
-    const int KB = W / 32, MTW = W / 64, NS = (prec == SDF_BF16X3) ? 2 : 1;
-    for (int w = 0; w < 4; ++w)
+    const int NWV = W >= 128 ? 8 : 4;  // waves per workgroup, as in the kernel
+    const int KB = W / 32, MTW = W / (16 * NWV), NS = (prec == SDF_BF16X3) ? 2 : 1;
+    for (int w = 0; w < NWV; ++w)
       for (int kb = 0; kb < KB; ++kb)
         for (int ml = 0; ml < MTW; ++ml)
           for (int part = 0; part < NS; ++part)
@@ -345,8 +346,9 @@ hipError_t launch(const sdf_net* net, const KArgs& a, hipStream_t s) {
   } else {
     const int pts = (net->prec == SDF_BF16X3) ? 32 : 64;  // points per workgroup
     dim3 grid((unsigned)((a.n + pts - 1) / pts));
+    dim3 block16(W >= 128 ? 512 : 256);  // 8 waves (2 per SIMD) from width 128 up
 #define K16(WW, PP) \
-  if (W == WW && net->prec == PP) hipLaunchKernelGGL((sdf_k16<WW, PP, MODE>), grid, block, 0, s, a);
+  if (W == WW && net->prec == PP) hipLaunchKernelGGL((sdf_k16<WW, PP, MODE>), grid, block16, 0, s, a);
     K16(64, PREC_BF16) K16(128, PREC_BF16) K16(256, PREC_BF16)
     K16(64, PREC_FP16) K16(128, PREC_FP16) K16(256, PREC_FP16)
     K16(64, PREC_BF16X3) K16(128, PREC_BF16X3) K16(256, PREC_BF16X3)

@@ -84,10 +84,11 @@ __device__ __forceinline__ void chunk_acquire(int gc, int nch, const unsigned ch
   if (gc + kNBuf - 1 < nch) issue_chunk<G>(stream, gc + kNBuf - 1, ring, wave, lane);
 }
 
-// log2(1 + 2^y), the rescaled softplus, with hardware exp2/log2.
+// log2(1 + 2^y), the rescaled softplus, with hardware exp2/log2:
+// max(y, 0) + log2(1 + 2^-|y|), where max(y, 0) = (y + |y|) / 2 exactly.
 __device__ __forceinline__ float softplus2(float y) {
   const float e = __builtin_amdgcn_exp2f(-__builtin_fabsf(y));
-  return __builtin_fmaxf(y, 0.0f) + __builtin_amdgcn_logf(1.0f + e);
+  return __builtin_fmaf(y + __builtin_fabsf(y), 0.5f, __builtin_amdgcn_logf(1.0f + e));
 }
 
 template <int PREC>

@@ -14,6 +14,8 @@
 // registers (1 - 2^{-r}, r stored as 16-bit).  Layer 1 (K = 3), the skip
 // x-columns, the output layer, the normal (Eq. 2) and the move to the contact
 // point (Eq. 3) are FP32 VALU; per-point sums across waves go through LDS.
+#include <type_traits>
+
 #include "sdf_device.hpp"
 
 namespace sdfc {
@@ -23,14 +25,15 @@ namespace sdfc {
 // which keeps about 16 significant bits (compensated "BF16x3").
 template <int W, int NS>
 struct GeoB {
+  static constexpr int NWV = W >= 128 ? 8 : 4;  // waves per workgroup (2 per SIMD when 8)
   static constexpr int NCT = NS == 1 ? 4 : 2;  // column tiles (16 points each)
   static constexpr int PTS = 16 * NCT;         // points per workgroup
-  static constexpr int FW = W / 4;             // features per wave
+  static constexpr int FW = W / NWV;           // features per wave
   static constexpr int MTW = FW / 16;          // M-tiles per wave
   static constexpr int KB = W / 32;            // K-blocks of 32 per layer
   static constexpr int D = KB < 2 ? KB : 2;    // weight prefetch depth in K-steps
   static constexpr int WAVE_BYTES = KB * MTW * NS * kFrag;  // one wave's slice of a layer
-  static constexpr int LAYER_BYTES = 4 * WAVE_BYTES;
+  static constexpr int LAYER_BYTES = NWV * WAVE_BYTES;
   static constexpr int ACT_BYTES = KB * NCT * kFrag;        // one exchange buffer part
   static constexpr int NS_ = NS;
   static_assert(MTW >= 1 && KB % D == 0, "shape");
@@ -70,17 +73,18 @@ __device__ __forceinline__ void split4(f32x4 v, uint2& hi, uint2& lo) {
 }
 
 template <int W, int PREC, int MODE>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ void __attribute__((amdgpu_flat_work_group_size(64 * (W >= 128 ? 8 : 4), 64 * (W >= 128 ? 8 : 4))))
 sdf_k16(const KArgs a) {
   constexpr int NS = PREC == PREC_BF16X3 ? 2 : 1;
   constexpr int OP = PREC == PREC_BF16X3 ? PREC_BF16 : PREC;  // MFMA operand type
   using G = GeoB<W, NS>;
+  constexpr int NWV = G::NWV, NT = 64 * NWV;
   constexpr SmallLayout SL{W};
   constexpr int MTW = G::MTW, KB = G::KB, NCT = G::NCT, D = G::D, PTS = G::PTS;
 
   __shared__ __attribute__((aligned(16))) unsigned char act[2][NS][G::ACT_BYTES];
   __shared__ __attribute__((aligned(16))) float sm[SL.floats()];
-  __shared__ __attribute__((aligned(16))) f32x4 red[4][PTS];
+  __shared__ __attribute__((aligned(16))) f32x4 red[NWV][PTS];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -100,7 +104,7 @@ sdf_k16(const KArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) x[ct][c] = ok ? a.pts_in[3 * p + c] : 0.0f;
   }
-  for (int i = tid; i < SL.floats() / 4; i += kBlock)
+  for (int i = tid; i < SL.floats() / 4; i += NT)
     reinterpret_cast<f32x4*>(sm)[i] = reinterpret_cast<const f32x4*>(a.small)[i];
 
   // first weight fragments (forward layer 2)
@@ -243,33 +247,44 @@ sdf_k16(const KArgs a) {
           put(out, mt, ct, r, stk[l][mt][ct]);
         }
     } else {
+      // output layer f = (w_o/kappa) . r_L and the reverse-sweep seed
+      // d_L = w_o (1 - 2^-r_L); SKIPG: layer L is also the skip layer.
+      auto last_epi = [&](auto SKIPG) {
 #pragma unroll
-      for (int mt = 0; mt < MTW; ++mt) {
-        const f32x4 wf = *reinterpret_cast<const f32x4*>(&sm[SL.wof() + 16 * (MTW * wave + mt) + 4 * g]);
-        const f32x4 wb = *reinterpret_cast<const f32x4*>(&sm[SL.wob() + 16 * (MTW * wave + mt) + 4 * g]);
+        for (int mt = 0; mt < MTW; ++mt) {
+          const f32x4 wf = *reinterpret_cast<const f32x4*>(&sm[SL.wof() + 16 * (MTW * wave + mt) + 4 * g]);
+          const f32x4 wb = *reinterpret_cast<const f32x4*>(&sm[SL.wob() + 16 * (MTW * wave + mt) + 4 * g]);
+          f32x4 wg[4];
+          if constexpr (decltype(SKIPG)::value)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-          f32x4 d;
+            for (int i = 0; i < 4; ++i) wg[i] = *reinterpret_cast<const f32x4*>(&sm[SL.skg() + 4 * feat(mt, i)]);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float r = softplus2(acc[mt][ct][i]);
-            fpart[ct] = __builtin_fmaf(wf[i], r, fpart[ct]);
-            d[i] = __builtin_fmaf(-wb[i], __builtin_amdgcn_exp2f(-r), wb[i]);  // w_o (1 - 2^-r)
-          }
-          if constexpr (MODE != MODE_QUERY) {
-            if (l == skip) {
+          for (int ct = 0; ct < NCT; ++ct) {
+            f32x4 d;
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[SL.skg() + 4 * feat(mt, i)]);
-                gx[ct][0] = __builtin_fmaf(w.x, d[i], gx[ct][0]);
-                gx[ct][1] = __builtin_fmaf(w.y, d[i], gx[ct][1]);
-                gx[ct][2] = __builtin_fmaf(w.z, d[i], gx[ct][2]);
-              }
+            for (int i = 0; i < 4; ++i) {
+              const float r = softplus2(acc[mt][ct][i]);
+              fpart[ct] = __builtin_fmaf(wf[i], r, fpart[ct]);
+              d[i] = __builtin_fmaf(-wb[i], __builtin_amdgcn_exp2f(-r), wb[i]);
             }
-            put(out, mt, ct, d, nullptr);
+            if constexpr (MODE != MODE_QUERY) {
+              if constexpr (decltype(SKIPG)::value) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                  gx[ct][0] = __builtin_fmaf(wg[i].x, d[i], gx[ct][0]);
+                  gx[ct][1] = __builtin_fmaf(wg[i].y, d[i], gx[ct][1]);
+                  gx[ct][2] = __builtin_fmaf(wg[i].z, d[i], gx[ct][2]);
+                }
+              }
+              put(out, mt, ct, d, nullptr);
+            }
           }
         }
-      }
+      };
+      if (MODE != MODE_QUERY && l == skip)
+        last_epi(std::true_type{});
+      else
+        last_epi(std::false_type{});
     }
     __syncthreads();
   }
@@ -290,34 +305,41 @@ sdf_k16(const KArgs a) {
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) acc[mt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
       contract(acc, in, layer, next);
+      // d_{l-1} = g (1 - 2^-r_{l-1}); TOX: fold d_{l-1} into grad x through the
+      // layer-1 weights (l == 2) or the skip layer's x-columns (l - 1 == skip).
+      auto bwd_epi = [&](auto TOX) {
 #pragma unroll
-      for (int mt = 0; mt < MTW; ++mt) {
-        f32x4 wg[4];
-        const bool to_x = (l - 1 == skip) || (l == 2);
-        if (to_x) {
-          const int off = (l == 2) ? SL.l1g() : SL.skg();
+        for (int mt = 0; mt < MTW; ++mt) {
+          f32x4 wg[4];
+          if constexpr (decltype(TOX)::value) {
+            const int off = (l == 2) ? SL.l1g() : SL.skg();
 #pragma unroll
-          for (int i = 0; i < 4; ++i) wg[i] = *reinterpret_cast<const f32x4*>(&sm[off + 4 * feat(mt, i)]);
-        }
-#pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-          f32x4 r = unpack4<OP>(stk[l - 1][mt][ct][0]);
-          if constexpr (NS == 2) r += unpack4<OP>(stk[l - 1][mt][ct][1]);
-          f32x4 d;
-#pragma unroll
-          for (int i = 0; i < 4; ++i)  // d_{l-1} = g (1 - 2^-r_{l-1})
-            d[i] = __builtin_fmaf(-acc[mt][ct][i], __builtin_amdgcn_exp2f(-r[i]), acc[mt][ct][i]);
-          if (to_x) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              gx[ct][0] = __builtin_fmaf(wg[i].x, d[i], gx[ct][0]);
-              gx[ct][1] = __builtin_fmaf(wg[i].y, d[i], gx[ct][1]);
-              gx[ct][2] = __builtin_fmaf(wg[i].z, d[i], gx[ct][2]);
-            }
+            for (int i = 0; i < 4; ++i) wg[i] = *reinterpret_cast<const f32x4*>(&sm[off + 4 * feat(mt, i)]);
           }
-          if (l > 2) put(out, mt, ct, d, nullptr);
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            f32x4 r = unpack4<OP>(stk[l - 1][mt][ct][0]);
+            if constexpr (NS == 2) r += unpack4<OP>(stk[l - 1][mt][ct][1]);
+            f32x4 d;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              d[i] = __builtin_fmaf(-acc[mt][ct][i], __builtin_amdgcn_exp2f(-r[i]), acc[mt][ct][i]);
+            if constexpr (decltype(TOX)::value) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                gx[ct][0] = __builtin_fmaf(wg[i].x, d[i], gx[ct][0]);
+                gx[ct][1] = __builtin_fmaf(wg[i].y, d[i], gx[ct][1]);
+                gx[ct][2] = __builtin_fmaf(wg[i].z, d[i], gx[ct][2]);
+              }
+            }
+            if (l > 2) put(out, mt, ct, d, nullptr);
+          }
         }
-      }
+      };
+      if (l == 2 || l - 1 == skip)
+        bwd_epi(std::true_type{});
+      else
+        bwd_epi(std::false_type{});
       if (l > 2) __syncthreads();
     }
   }
@@ -336,8 +358,9 @@ sdf_k16(const KArgs a) {
   __syncthreads();
   // waves 0..NCT-1 finish the points of column tile `wave`
   if (wave < NCT) {
-    const f32x4 s = red[0][16 * wave + col] + red[1][16 * wave + col] + red[2][16 * wave + col] +
-                    red[3][16 * wave + col];
+    f32x4 s = red[0][16 * wave + col];
+#pragma unroll
+    for (int w = 1; w < NWV; ++w) s += red[w][16 * wave + col];
     float px = x[0][0], py = x[0][1], pz = x[0][2];
 #pragma unroll
     for (int ct = 1; ct < NCT; ++ct)

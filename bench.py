@@ -24,6 +24,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3}  # MI355X dense MFMA
+KERNEL_SOURCES = ["paper_2110_01614_amd/csrc/sdf_k16.hip", "paper_2110_01614_amd/csrc/sdf_device.hpp",
+                  "paper_2110_01614_amd/csrc/sdf_layout.hpp", "paper_2110_01614_amd/csrc/sdf_api.cpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sdf_k16_cloth1m.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    record, or None when that record does not describe the current kernel."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("precision") != precision:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def copy_probe(mib: int):
+    """A plain device copy of known size, for calibrating the HBM counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 3}), flush=True)
 
 
 def flops_per_point(spec) -> int:
@@ -99,7 +136,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the collision path shards across GPUs with no exchange "
               "(each GPU takes a contiguous slice of vertices), so only --gpus 1 is run.", file=sys.stderr)
@@ -153,10 +195,13 @@ def main():
                                "N(0,0.01) jitter, seed 2) through 3->256x8->1 softplus(beta=100) "
                                "MLP, input re-fed at layer 5, N(0,0.02) weights seed 0; "
                                "collide_project in place, eps 0.005",
-                   "points": n, "flops_per_point": fpp, "launch": "1 kernel / step, 64 points "
-                   "per 256-thread workgroup"},
+                   "points": n, "flops_per_point": fpp,
+                   "launch": "1 kernel / step; BF16/FP16: 64 points per 512-thread workgroup, "
+                             "BF16x3: 32 points, FP32: persistent 256-thread workgroups",
+                   "kernel_source_hash": kernel_source_hash()},
         "roofline": {"bound": "mfma", "achieved": head["tflops"], "peak": PEAK_TFLOPS[args.precision],
-                     "unit": "TFLOP/s", "frac": head["mfma_frac"], "traffic": None},
+                     "unit": "TFLOP/s", "frac": head["mfma_frac"],
+                     "traffic": measured_traffic(args.precision)},
         "precisions": results,
         "paper_context": "Table 1 / abstract: ~1M queries in ~300 ms on a Tesla T4 (TensorFlow, "
                          "Fourier features + 4 or 8 FC x 256, ReLU)",

@@ -107,6 +107,27 @@ int sdf_query_grad(const sdf_net* net, const float* pts, int64_t n, float* sdf, 
 int collide_project(const sdf_net* net, float* pts, int64_t n, float eps, float* sdf,
                     float* normal, uint8_t* hit, void* stream);
 
+/* ---- fitting (Sec. 3.1): MLP regressed onto sampled signed distances ---- */
+
+/* Device workspace bytes sdf_train_step needs for a batch of n points with
+ * this network shape (FP32 only), or -1 on a malformed/unsupported desc.  The
+ * batch is processed in chunks, so the size stops growing beyond 65536 points. */
+int64_t sdf_train_workspace_bytes(const sdf_net_desc* desc, int64_t n);
+
+/* One fitting step, all in FP32 on the current device: the clamped-L1 loss
+ * loss = mean_i |clamp(f(p_i)) - clamp(s_i)| (clamp to [-delta, delta]; the
+ * paper's L1 loss, Sec. 3.1) and its gradient with respect to every parameter.
+ * params: device float32, the flat layout of sdf_param_count (read);
+ * pts: device float32 [n][3]; target: device float32 [n] signed distances;
+ * grad_params: device float32, same layout as params (overwritten);
+ * loss: device float32 [1] (overwritten); workspace: device memory of at least
+ * sdf_train_workspace_bytes(desc, n) bytes, 256-byte aligned, caller-owned.
+ * The result does not depend on thread scheduling (fixed reduction order).
+ * desc->precision must be SDF_FP32.  Errors as for the query entry points. */
+int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* pts,
+                   const float* target, int64_t n, float delta, float* grad_params, float* loss,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char* sdf_last_error(void);
 

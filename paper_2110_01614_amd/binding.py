@@ -56,6 +56,10 @@ def _load():
     lib.collide_project.argtypes = [vp, vp, i64, f32, vp, vp, vp, vp]
     lib.sdf_last_error.restype = ctypes.c_char_p
     lib.sdf_last_error.argtypes = []
+    lib.sdf_train_workspace_bytes.restype = i64
+    lib.sdf_train_workspace_bytes.argtypes = [desc_p, i64]
+    lib.sdf_train_step.restype = ctypes.c_int
+    lib.sdf_train_step.argtypes = [desc_p, vp, vp, vp, i64, f32, vp, vp, vp, ctypes.c_size_t, vp]
     return lib
 
 
@@ -184,3 +188,69 @@ class SdfNet:
             outs["hit"] = torch.empty(n, device=pts.device, dtype=torch.uint8)
         collide_project(self.handle, pts, n, eps, outs.get("sdf"), outs.get("normal"), outs.get("hit"))
         return outs
+
+
+# ------------------------------------------------------------------ fitting
+
+def sdf_train_workspace_bytes(desc: sdf_net_desc, n: int) -> int:
+    v = int(lib.sdf_train_workspace_bytes(ctypes.byref(desc), int(n)))
+    if v < 0:
+        raise SdfError(SDF_EINVAL, sdf_last_error())
+    return v
+
+
+def sdf_train_step(desc, params, pts, target, n, delta, grad_params, loss, workspace, ws_bytes,
+                   stream=None):
+    return _check(lib.sdf_train_step(ctypes.byref(desc), _ptr(params), _ptr(pts), _ptr(target), int(n),
+                                     float(delta), _ptr(grad_params), _ptr(loss), _ptr(workspace),
+                                     int(ws_bytes), _stream(stream)))
+
+
+class SdfFit:
+    """Owns the device workspace of FP32 fitting steps for one network shape."""
+
+    def __init__(self, spec, max_n, device=0):
+        import torch
+        self.spec = spec
+        self.desc = make_desc(spec.widths, spec.skip, spec.beta, "fp32")
+        self.device = torch.device("cuda", device)
+        with torch.cuda.device(self.device):
+            self.ws_bytes = sdf_train_workspace_bytes(self.desc, max_n)
+        self.max_n = max_n
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def step(self, params, pts, target, delta=0.1):
+        """(loss, grad) for flat float32 CUDA parameters; both are new tensors."""
+        import torch
+        n = pts.shape[0]
+        if n > self.max_n:
+            raise ValueError("batch larger than the workspace was sized for")
+        for t, shape in ((params, None), (pts, (n, 3)), (target, (n,))):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                raise ValueError("params, pts and target must be contiguous float32 CUDA tensors")
+            if shape is not None and tuple(t.shape) != shape:
+                raise ValueError("pts must be [n, 3] and target [n]")
+        grad = torch.empty_like(params)
+        loss = torch.empty(1, device=params.device, dtype=torch.float32)
+        sdf_train_step(self.desc, params, pts, target, n, delta, grad, loss, self.workspace, self.ws_bytes)
+        return loss, grad
+
+
+def fit_loss(fit: SdfFit, params, pts, target, delta=0.1):
+    """Differentiable clamped-L1 fitting loss: the gradient w.r.t. params comes
+    from the library's reverse sweep and weight-gradient kernels."""
+    import torch
+
+    class _FitLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, p):
+            loss, grad = fit.step(p.detach().contiguous(), pts, target, delta)
+            ctx.save_for_backward(grad)
+            return loss[0]
+
+        @staticmethod
+        def backward(ctx, gout):
+            (grad,) = ctx.saved_tensors
+            return gout * grad
+
+    return _FitLoss.apply(params)

@@ -17,6 +17,11 @@ template <int W, int PREC, int MODE>
 __global__ void sdf_k16(const KArgs a);
 template <int W, int MODE>
 __global__ void sdf_k32(const KArgs a);
+__global__ void pack_fp32_kernel(TrainNet t, const float* P, float* stream, float* small);
+__global__ void fill_kernel(float* p, int64_t n, float v);
+__global__ void loss_reduce_kernel(const float* terms, int64_t n, float* loss);
+__global__ void wgrad_kernel(TrainNet t, const float* E, const float* H, const float* U, int64_t n,
+                             float* grad);
 }  // namespace sdfc
 
 using namespace sdfc;
@@ -418,6 +423,160 @@ int sdf_query_grad(const sdf_net* net, const float* pts, int64_t n, float* sdf, 
 int collide_project(const sdf_net* net, float* pts, int64_t n, float eps, float* sdf,
                     float* normal, uint8_t* hit, void* stream) {
   return run<MODE_PROJECT>(net, pts, pts, n, eps, sdf, nullptr, normal, hit, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ fitting
+
+namespace {
+
+constexpr int64_t kTrainChunk = 65536;  // points per chunk of a fitting step
+
+struct TrainLayout {  // byte offsets inside the caller's workspace
+  size_t stream, small, scratch, E, H, U, loss, total;
+  int64_t chunk;
+};
+
+TrainLayout train_layout(int W, int L, int64_t n, int slots) {
+  TrainLayout t{};
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const int64_t chunk = n < kTrainChunk ? (n > 0 ? n : 1) : kTrainChunk;
+  size_t o = 0;
+  t.stream = o;
+  o = up(o + 2 * (size_t)(L - 1) * (W / 16) * (W / 16) * kFrag);
+  t.small = o;
+  o = up(o + (size_t)SmallLayout{W}.floats() * 4);
+  t.scratch = o;
+  o = up(o + (size_t)slots * (kLMax - 1) * 4 * (W / 16) * 64 * 16);
+  t.E = o;
+  o = up(o + (size_t)L * chunk * W * 4);
+  t.H = o;
+  o = up(o + (size_t)(L + 1) * chunk * (W + 16) * 4);
+  t.U = o;
+  o = up(o + (size_t)chunk * 16 * 4);
+  t.loss = o;
+  o = up(o + (size_t)chunk * 4);
+  t.total = o;
+  t.chunk = chunk;
+  return t;
+}
+
+int train_check(const sdf_net_desc* desc, int* W, int* L, int* skip) {
+  int rc = check_desc(desc, W, L, skip);
+  if (rc) return rc;
+  rc = check_supported(*W, desc);
+  if (rc) return rc;
+  if (desc->precision != SDF_FP32) return fail(SDF_EUNSUPPORTED, "fitting runs in FP32 (precision must be SDF_FP32)");
+  return SDF_OK;
+}
+
+int device_cus(int* cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess || *cus < 1) return fail(SDF_EDEVICE, "hipDeviceGetAttribute(CU count)");
+  return SDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sdf_train_workspace_bytes(const sdf_net_desc* desc, int64_t n) {
+  g_err.clear();
+  int W, L, skip, cus;
+  if (train_check(desc, &W, &L, &skip) != SDF_OK || n < 0) return -1;
+  if (device_cus(&cus) != SDF_OK) return -1;
+  return (int64_t)train_layout(W, L, n, cus).total;
+}
+
+int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* pts,
+                   const float* target, int64_t n, float delta, float* grad_params, float* loss,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+  g_err.clear();
+  int W, L, skip;
+  int rc = train_check(desc, &W, &L, &skip);
+  if (rc) return rc;
+  if (!params || !grad_params || !loss || (n > 0 && (!pts || !target || !workspace)))
+    return fail(SDF_EINVAL, "NULL pointer argument");
+  if (n < 0) return fail(SDF_EINVAL, "n < 0");
+  if (!std::isfinite(delta) || delta <= 0.0f) return fail(SDF_EINVAL, "delta must be finite and > 0");
+  if (!aligned4(params) || !aligned4(pts) || !aligned4(target) || !aligned4(grad_params) ||
+      !aligned4(loss) || ((uintptr_t)workspace & 255u))
+    return fail(SDF_EINVAL, "arrays must be 4-byte aligned, the workspace 256-byte aligned");
+  if (n > ((int64_t)1 << 40)) return fail(SDF_EINVAL, "n too large");
+  int cus;
+  rc = device_cus(&cus);
+  if (rc) return rc;
+  const TrainLayout lay = train_layout(W, L, n, cus);
+  if (n > 0 && workspace_bytes < lay.total)
+    return fail(SDF_EINVAL, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+  const hipStream_t s = (hipStream_t)stream;
+  const int64_t np = count_params(desc);
+
+  TrainNet t{};
+  t.W = W;
+  t.L = L;
+  t.skip = skip;
+  t.kappa = (float)((double)desc->beta / std::log(2.0));
+  {
+    int64_t o = 0;
+    int prev = 3;
+    for (int l = 1; l <= L; ++l) {
+      const int k = prev + (l == skip ? 3 : 0);
+      t.offW[l] = o;
+      o += (int64_t)W * k;
+      t.offb[l] = o;
+      o += W;
+      prev = W;
+    }
+    t.offo = o;
+  }
+  hipLaunchKernelGGL(fill_kernel, dim3(1024), dim3(256), 0, s, grad_params, np, 0.0f);
+  hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, s, loss, (int64_t)1, 0.0f);
+  if (n == 0) {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SDF_OK : hip_fail(e, "kernel launch");
+  }
+  unsigned char* ws = (unsigned char*)workspace;
+  float* d_stream = (float*)(ws + lay.stream);
+  float* d_small = (float*)(ws + lay.small);
+  hipLaunchKernelGGL(pack_fp32_kernel, dim3(2048), dim3(256), 0, s, t, params, d_stream, d_small);
+
+  KArgs a{};
+  a.stream = (const unsigned char*)d_stream;
+  a.small = d_small;
+  a.scratch = (float*)(ws + lay.scratch);
+  a.L = L;
+  a.skip = skip;
+  a.nch = (L - 1) * (int)((size_t)(W / 16) * (W / 16) * kFrag / std::min<size_t>((size_t)(W / 16) * (W / 16) * kFrag, 32768)) * 2;
+  a.ws_E = (float*)(ws + lay.E);
+  a.ws_H = (float*)(ws + lay.H);
+  a.ws_U = (float*)(ws + lay.U);
+  a.ws_loss = (float*)(ws + lay.loss);
+  a.delta = delta;
+  a.inv_n = (float)(1.0 / (double)n);
+  a.inv_kappa = 1.0f / t.kappa;
+  const int RB = W / 64 > 0 ? W / 64 : 1, CB = W / 64 + 1;
+  const int items = RB + (L - 1) * RB * CB + CB;
+  for (int64_t c0 = 0; c0 < n; c0 += lay.chunk) {
+    const int64_t cn = std::min<int64_t>(lay.chunk, n - c0);
+    a.pts_in = pts + 3 * c0;
+    a.target = target + c0;
+    a.n = cn;
+    a.ntiles = (int)((cn + kPtsPerBlock - 1) / kPtsPerBlock);
+    dim3 grid((unsigned)std::min<int64_t>(a.ntiles, cus));
+#define KT(WW) \
+  if (W == WW) hipLaunchKernelGGL((sdf_k32<WW, MODE_TRAIN>), grid, dim3(kBlock), 0, s, a);
+    KT(64) KT(128) KT(256)
+#undef KT
+    hipLaunchKernelGGL(wgrad_kernel, dim3(items), dim3(256), 0, s, t, a.ws_E, a.ws_H, a.ws_U, cn, grad_params);
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, s, a.ws_loss, cn, loss);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SDF_OK : hip_fail(e, "kernel launch");
 }
 
 }  // extern "C"

@@ -15,7 +15,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
-enum { MODE_QUERY = 0, MODE_GRAD = 1, MODE_PROJECT = 2 };
+enum { MODE_QUERY = 0, MODE_GRAD = 1, MODE_PROJECT = 2, MODE_TRAIN = 3 };
 enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2, PREC_BF16X3 = 3 };
 
 // Everything a launch needs; passed by value in the kernel argument segment.
@@ -36,6 +36,23 @@ struct KArgs {
   int skip;              // 0 or 2..L
   int nch;               // chunks streamed per tile
   int ntiles;            // ceil(n / 64)
+  // fitting (MODE_TRAIN) only: per-point targets and the per-chunk workspace
+  const float* target;   // [n] signed distances
+  float* ws_E;           // [L][n][W]: dLoss/dz_l per point
+  float* ws_H;           // [L+1][n][W+16]: h_l, then x, y, z, 1, zeros (h_0 slot: x, y, z, 1 only)
+  float* ws_U;           // [n][16]: dLoss/df, zeros
+  float* ws_loss;        // [n]: |clamp(f) - clamp(s)| / n_total
+  float delta;           // clamp of the L1 loss
+  float inv_n;           // 1 / n_total (the whole batch, not the chunk)
+  float inv_kappa;       // 1 / (beta log2 e): h = r / kappa
+};
+
+// Geometry of one network for the fitting kernels (flat parameter layout).
+struct TrainNet {
+  int W, L, skip;
+  float kappa;
+  int64_t offW[kLMax + 1], offb[kLMax + 1], offo;  // offsets into the flat array
+  __host__ __device__ int K(int l) const { return (l == 1 ? 3 : W) + (l == skip ? 3 : 0); }
 };
 
 __device__ __forceinline__ unsigned lds_u32(const void* p) {
@@ -56,6 +73,14 @@ __device__ __forceinline__ void dma16(const void* g, unsigned lds) {
 template <int N>
 __device__ __forceinline__ void vm_wait_barrier() {
   asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"I"(N) : "memory");
+}
+
+// Workgroup barrier that orders LDS traffic only: every wave's LDS reads and
+// writes are complete before any wave passes.  Unlike __syncthreads() it does
+// not wait for this wave's outstanding global loads (weight prefetches for the
+// next layer stay in flight across the barrier).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // Copy chunk `c` of the weight stream into ring slot c % kNBuf.

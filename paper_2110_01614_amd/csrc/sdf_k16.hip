@@ -18,6 +18,13 @@
 
 #include "sdf_device.hpp"
 
+#ifndef SDF_K16_D
+#define SDF_K16_D 2
+#endif
+#ifndef SDF_K16_BDB
+#define SDF_K16_BDB 1
+#endif
+
 namespace sdfc {
 
 // NS = 1: plain 16-bit operands.  NS = 2: every operand is carried as a BF16
@@ -31,7 +38,12 @@ struct GeoB {
   static constexpr int FW = W / NWV;           // features per wave
   static constexpr int MTW = FW / 16;          // M-tiles per wave
   static constexpr int KB = W / 32;            // K-blocks of 32 per layer
-  static constexpr int D = KB < 2 ? KB : 2;    // weight prefetch depth in K-steps
+  static constexpr int DMAX = NS == 2 ? 2 : SDF_K16_D;
+  static constexpr int D = KB < DMAX ? KB : DMAX;  // weight prefetch depth in K-steps
+  // r_1..r_LS of the stack live in LDS (the reverse sweep reads them last);
+  // the rest stay in registers.
+  static constexpr int LS = W == 256 ? 1 : 0;
+  static constexpr int STK_BYTES = (LS > 0 ? LS : 1) * NWV * MTW * NCT * NS * 64 * 8;
   static constexpr int WAVE_BYTES = KB * MTW * NS * kFrag;  // one wave's slice of a layer
   static constexpr int LAYER_BYTES = NWV * WAVE_BYTES;
   static constexpr int ACT_BYTES = KB * NCT * kFrag;        // one exchange buffer part
@@ -84,7 +96,9 @@ sdf_k16(const KArgs a) {
 
   __shared__ __attribute__((aligned(16))) unsigned char act[2][NS][G::ACT_BYTES];
   __shared__ __attribute__((aligned(16))) float sm[SL.floats()];
-  __shared__ __attribute__((aligned(16))) f32x4 red[NWV][PTS];
+  __shared__ __attribute__((aligned(16))) f32x4 xs[PTS];  // the workgroup's points
+  __shared__ __attribute__((aligned(16))) uint2 stk_lds[G::STK_BYTES / 8];
+  __shared__ __attribute__((aligned(16))) f32x4 red[NWV][PTS];  // per wave: f, grad x partials
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -95,14 +109,16 @@ sdf_k16(const KArgs a) {
   const unsigned char* fwd = a.stream;  // layers 2..L, LAYER_BYTES each
   const unsigned char* rev = a.stream + (size_t)(L - 1) * G::LAYER_BYTES;  // layers L..2
 
-  // ---- points of the lane's column tiles, small weights ----
-  float x[NCT][3];
-#pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) {
-    const int64_t p = base + 16 * ct + col;
-    const bool ok = p < a.n;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) x[ct][c] = ok ? a.pts_in[3 * p + c] : 0.0f;
+  // ---- points (to LDS), small weights ----
+  if (tid < PTS) {
+    const int64_t p = base + tid;
+    f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (p < a.n) {
+      v[0] = a.pts_in[3 * p];
+      v[1] = a.pts_in[3 * p + 1];
+      v[2] = a.pts_in[3 * p + 2];
+    }
+    xs[tid] = v;
   }
   for (int i = tid; i < SL.floats() / 4; i += NT)
     reinterpret_cast<f32x4*>(sm)[i] = reinterpret_cast<const f32x4*>(a.small)[i];
@@ -124,8 +140,13 @@ sdf_k16(const KArgs a) {
     const int m = MTW * wave + mt;
     return ((m >> 1) * NCT + ct) * kFrag + lane * 16 + 8 * (m & 1);
   };
+  uint2 stk[kLMax][MTW][NCT][NS];  // r_l of the wave's rows, l = LS+1..L-1 (registers)
+  auto stk_at = [&](int l, int mt, int ct, int ps) -> uint2& {
+    return stk_lds[(((((l - 1) * NWV + wave) * MTW + mt) * NCT + ct) * NS + ps) * 64 + lane];
+  };
   // Store v (FP32) as the wave's operand rows: 16-bit (NS = 1) or a BF16 pair.
-  auto put = [&](unsigned char* out, int mt, int ct, f32x4 v, uint2* keep) {
+  // keep_l: stack layer to record v in (0: none).
+  auto put = [&](unsigned char* out, int mt, int ct, f32x4 v, int keep_l) {
     uint2 p[NS];
     if constexpr (NS == 1)
       p[0] = pack4<OP>(v);
@@ -134,17 +155,23 @@ sdf_k16(const KArgs a) {
 #pragma unroll
     for (int ps = 0; ps < NS; ++ps) {
       *reinterpret_cast<uint2*>(out + ps * G::ACT_BYTES + act_off(mt, ct)) = p[ps];
-      if (keep) keep[ps] = p[ps];
+      if (keep_l > 0 && keep_l <= G::LS)
+        stk_at(keep_l, mt, ct, ps) = p[ps];
+      else if (keep_l > G::LS)
+        stk[keep_l][mt][ct][ps] = p[ps];
     }
   };
 
-  uint2 stk[kLMax][MTW][NCT][NS];  // r_l of the wave's rows, l = 1..L-1
-  float fpart[NCT], gx[NCT][3];
+  // Per-point partial sums of this wave (f and grad x) go to red[wave]: the lane
+  // groups are summed with shuffles, then lanes 0..15 write or accumulate.
+  auto flush = [&](int ct, f32x4 v, bool accumulate) {
 #pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) {
-    fpart[ct] = 0.0f;
-    gx[ct][0] = gx[ct][1] = gx[ct][2] = 0.0f;
-  }
+    for (int c = 0; c < 4; ++c) v[c] = sum_lane_groups(v[c]);
+    if (g == 0) {
+      if (accumulate) v += red[wave][16 * ct + col];
+      red[wave][16 * ct + col] = v;
+    }
+  };
 
   // ---- layer 1: y = kappa (W1 x + b1) ----
 #pragma unroll
@@ -154,29 +181,37 @@ sdf_k16(const KArgs a) {
     for (int i = 0; i < 4; ++i) w4[i] = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * feat(mt, i)]);
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
+      const f32x4 x = xs[16 * ct + col];
       f32x4 r;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        r[i] = softplus2(__builtin_fmaf(w4[i].x, x[ct][0],
-                                        __builtin_fmaf(w4[i].y, x[ct][1], __builtin_fmaf(w4[i].z, x[ct][2], w4[i].w))));
-      put(&act[0][0][0], mt, ct, r, stk[1][mt][ct]);
+        r[i] = softplus2(__builtin_fmaf(w4[i].x, x[0], __builtin_fmaf(w4[i].y, x[1], __builtin_fmaf(w4[i].z, x[2], w4[i].w))));
+      put(&act[0][0][0], mt, ct, r, 1);
     }
   }
-  __syncthreads();
+  lds_barrier();
 
   // One hidden layer's contraction for this wave: acc[mt][ct] += A(mt, kb) B(kb, ct)
   // with B from exchange buffer `in`; prefetches the next layer's first D K-steps
   // from `next` (nullptr: nothing follows).
   auto contract = [&](f32x4 (&acc)[MTW][NCT], const unsigned char* in, const unsigned char* layer,
                       const unsigned char* next) {
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      u32x4 Bv[NCT][NS];
+    constexpr int NB = SDF_K16_BDB ? 2 : 1;
+    u32x4 Bv[NB][NCT][NS];  // B operands of K-steps kb (in use) and kb + 1 (in flight)
+    auto loadB = [&](u32x4 (&dst)[NCT][NS], int kb) {
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
         for (int ps = 0; ps < NS; ++ps)
-          Bv[ct][ps] = *reinterpret_cast<const u32x4*>(in + ps * G::ACT_BYTES + (kb * NCT + ct) * kFrag + lane * 16);
+          dst[ct][ps] = *reinterpret_cast<const u32x4*>(in + ps * G::ACT_BYTES + (kb * NCT + ct) * kFrag + lane * 16);
+    };
+    if (NB == 2) loadB(Bv[0], 0);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      if (NB == 1)
+        loadB(Bv[0], kb);
+      else if (kb + 1 < KB)
+        loadB(Bv[(kb + 1) % NB], kb + 1);
       u32x4 Acur[MTW][NS];
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt)
@@ -194,15 +229,16 @@ sdf_k16(const KArgs a) {
 #pragma unroll
           for (int ps = 0; ps < NS; ++ps) Aq[kb % D][mt][ps] = *wfrag<G>(next, wave, nk - KB, mt, ps, lane);
       }
+      const auto& B = Bv[kb % NB];
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
           if constexpr (NS == 2) {  // small cross terms first
-            acc[mt][ct] = mfma16<OP>(Acur[mt][1], Bv[ct][0], acc[mt][ct]);
-            acc[mt][ct] = mfma16<OP>(Acur[mt][0], Bv[ct][1], acc[mt][ct]);
+            acc[mt][ct] = mfma16<OP>(Acur[mt][1], B[ct][0], acc[mt][ct]);
+            acc[mt][ct] = mfma16<OP>(Acur[mt][0], B[ct][1], acc[mt][ct]);
           }
-          acc[mt][ct] = mfma16<OP>(Acur[mt][0], Bv[ct][0], acc[mt][ct]);
+          acc[mt][ct] = mfma16<OP>(Acur[mt][0], B[ct][0], acc[mt][ct]);
         }
     }
   };
@@ -231,8 +267,10 @@ sdf_k16(const KArgs a) {
         for (int i = 0; i < 4; ++i) {
           const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[SL.skf() + 4 * feat(mt, i)]);
 #pragma unroll
-          for (int ct = 0; ct < NCT; ++ct)
-            acc[mt][ct][i] = __builtin_fmaf(w.x, x[ct][0], __builtin_fmaf(w.y, x[ct][1], __builtin_fmaf(w.z, x[ct][2], acc[mt][ct][i])));
+          for (int ct = 0; ct < NCT; ++ct) {
+            const f32x4 x = xs[16 * ct + col];
+            acc[mt][ct][i] = __builtin_fmaf(w.x, x[0], __builtin_fmaf(w.y, x[1], __builtin_fmaf(w.z, x[2], acc[mt][ct][i])));
+          }
         }
     }
     contract(acc, in, layer, next);
@@ -244,12 +282,15 @@ sdf_k16(const KArgs a) {
           f32x4 r;
 #pragma unroll
           for (int i = 0; i < 4; ++i) r[i] = softplus2(acc[mt][ct][i]);
-          put(out, mt, ct, r, stk[l][mt][ct]);
+          put(out, mt, ct, r, l);
         }
     } else {
       // output layer f = (w_o/kappa) . r_L and the reverse-sweep seed
       // d_L = w_o (1 - 2^-r_L); SKIPG: layer L is also the skip layer.
       auto last_epi = [&](auto SKIPG) {
+        f32x4 part[NCT];  // f, grad x partials of this wave's features
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) part[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
           const f32x4 wf = *reinterpret_cast<const f32x4*>(&sm[SL.wof() + 16 * (MTW * wave + mt) + 4 * g]);
@@ -264,29 +305,31 @@ sdf_k16(const KArgs a) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const float r = softplus2(acc[mt][ct][i]);
-              fpart[ct] = __builtin_fmaf(wf[i], r, fpart[ct]);
+              part[ct][0] = __builtin_fmaf(wf[i], r, part[ct][0]);
               d[i] = __builtin_fmaf(-wb[i], __builtin_amdgcn_exp2f(-r), wb[i]);
             }
             if constexpr (MODE != MODE_QUERY) {
               if constexpr (decltype(SKIPG)::value) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                  gx[ct][0] = __builtin_fmaf(wg[i].x, d[i], gx[ct][0]);
-                  gx[ct][1] = __builtin_fmaf(wg[i].y, d[i], gx[ct][1]);
-                  gx[ct][2] = __builtin_fmaf(wg[i].z, d[i], gx[ct][2]);
+                  part[ct][1] = __builtin_fmaf(wg[i].x, d[i], part[ct][1]);
+                  part[ct][2] = __builtin_fmaf(wg[i].y, d[i], part[ct][2]);
+                  part[ct][3] = __builtin_fmaf(wg[i].z, d[i], part[ct][3]);
                 }
               }
-              put(out, mt, ct, d, nullptr);
+              put(out, mt, ct, d, 0);
             }
           }
         }
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) flush(ct, part[ct], false);
       };
       if (MODE != MODE_QUERY && l == skip)
         last_epi(std::true_type{});
       else
         last_epi(std::false_type{});
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   // ---- reverse sweep over W_l^T, l = L..2 ----
@@ -308,6 +351,9 @@ sdf_k16(const KArgs a) {
       // d_{l-1} = g (1 - 2^-r_{l-1}); TOX: fold d_{l-1} into grad x through the
       // layer-1 weights (l == 2) or the skip layer's x-columns (l - 1 == skip).
       auto bwd_epi = [&](auto TOX) {
+        f32x4 part[NCT];  // grad x partials (components 1..3)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) part[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
           f32x4 wg[4];
@@ -318,8 +364,12 @@ sdf_k16(const KArgs a) {
           }
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
-            f32x4 r = unpack4<OP>(stk[l - 1][mt][ct][0]);
-            if constexpr (NS == 2) r += unpack4<OP>(stk[l - 1][mt][ct][1]);
+            uint2 q[NS];
+#pragma unroll
+            for (int ps = 0; ps < NS; ++ps)
+              q[ps] = (l - 1 <= G::LS) ? stk_at(l - 1, mt, ct, ps) : stk[l - 1][mt][ct][ps];
+            f32x4 r = unpack4<OP>(q[0]);
+            if constexpr (NS == 2) r += unpack4<OP>(q[1]);
             f32x4 d;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -327,50 +377,35 @@ sdf_k16(const KArgs a) {
             if constexpr (decltype(TOX)::value) {
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                gx[ct][0] = __builtin_fmaf(wg[i].x, d[i], gx[ct][0]);
-                gx[ct][1] = __builtin_fmaf(wg[i].y, d[i], gx[ct][1]);
-                gx[ct][2] = __builtin_fmaf(wg[i].z, d[i], gx[ct][2]);
+                part[ct][1] = __builtin_fmaf(wg[i].x, d[i], part[ct][1]);
+                part[ct][2] = __builtin_fmaf(wg[i].y, d[i], part[ct][2]);
+                part[ct][3] = __builtin_fmaf(wg[i].z, d[i], part[ct][3]);
               }
             }
-            if (l > 2) put(out, mt, ct, d, nullptr);
+            if (l > 2) put(out, mt, ct, d, 0);
           }
         }
+        if constexpr (decltype(TOX)::value)
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) flush(ct, part[ct], true);
       };
       if (l == 2 || l - 1 == skip)
         bwd_epi(std::true_type{});
       else
         bwd_epi(std::false_type{});
-      if (l > 2) __syncthreads();
+      if (l > 2) lds_barrier();
     }
   }
 
-  // ---- per-point sums across lane groups, then across waves ----
-#pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) {
-    f32x4 v = {sum_lane_groups(fpart[ct]), 0.0f, 0.0f, 0.0f};
-    if constexpr (MODE != MODE_QUERY) {
-      v[1] = sum_lane_groups(gx[ct][0]);
-      v[2] = sum_lane_groups(gx[ct][1]);
-      v[3] = sum_lane_groups(gx[ct][2]);
-    }
-    if (g == 0) red[wave][16 * ct + col] = v;
-  }
-  __syncthreads();
-  // waves 0..NCT-1 finish the points of column tile `wave`
+  // ---- per-point sums across waves; waves 0..NCT-1 finish column tile `wave` ----
+  lds_barrier();
   if (wave < NCT) {
     f32x4 s = red[0][16 * wave + col];
 #pragma unroll
     for (int w = 1; w < NWV; ++w) s += red[w][16 * wave + col];
-    float px = x[0][0], py = x[0][1], pz = x[0][2];
-#pragma unroll
-    for (int ct = 1; ct < NCT; ++ct)
-      if (wave == ct) {
-        px = x[ct][0];
-        py = x[ct][1];
-        pz = x[ct][2];
-      }
+    const f32x4 x = xs[16 * wave + col];
     const int64_t p = base + 16 * wave + col;
-    store_outputs<MODE>(a, p, p < a.n && g == 0, s[0] + a.bo, s[1], s[2], s[3], px, py, pz);
+    store_outputs<MODE>(a, p, p < a.n && g == 0, s[0] + a.bo, s[1], s[2], s[3], x[0], x[1], x[2]);
   }
 }
 

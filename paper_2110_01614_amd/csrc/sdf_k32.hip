@@ -10,6 +10,11 @@
 // per-workgroup scratch area (one slot per resident workgroup, reused tile
 // after tile) and the reverse sweep (Sec. 3.2) reads them back.  The grid is
 // persistent: workgroup b processes tiles b, b + gridDim.x, ...
+//
+// MODE_TRAIN (fitting, Sec. 3.1) runs the same two sweeps for the clamped-L1
+// loss: the reverse sweep is seeded with dLoss/df instead of 1, and every
+// layer's activations h_l and errors dLoss/dz_l are written to a workspace
+// from which the weight-gradient kernel (sdf_train.hip) forms sum_p e h^T.
 #include "sdf_device.hpp"
 
 namespace sdfc {
@@ -23,9 +28,20 @@ __device__ __forceinline__ void softplus_sigmoid(float y, float& r, float& s) {
   s = (y >= 0.0f) ? q : e * q;
 }
 
+// Workspace row pointers of point p (training): H_l row and E_l row.
+template <int W>
+__device__ __forceinline__ float* hrow(const KArgs& a, int l, int64_t p) {
+  return a.ws_H + ((size_t)l * a.n + p) * (W + 16);
+}
+template <int W>
+__device__ __forceinline__ float* erow(const KArgs& a, int l, int64_t p) {
+  return a.ws_E + ((size_t)(l - 1) * a.n + p) * W;
+}
+
 template <int W, int MODE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 1)))
 sdf_k32(const KArgs a) {
+  constexpr bool TRAIN = MODE == MODE_TRAIN;
   using G = Geo<W, true>;
   constexpr SmallLayout SL{W};
   constexpr int MT = G::MT, KB = G::KB, CH_MT = G::CH_MT, CPL = G::CPL;
@@ -75,6 +91,20 @@ sdf_k32(const KArgs a) {
         s4[i] = sg;
       }
       if constexpr (MODE != MODE_QUERY) sstk[mt * 64] = s4;
+      if constexpr (TRAIN)
+        if (valid) *reinterpret_cast<f32x4*>(hrow<W>(a, 1, p) + 16 * mt + 4 * g) = Rin[mt] * a.inv_kappa;
+    }
+    if constexpr (TRAIN) {
+      if (valid && g == 0) {  // h_0 slot: x, y, z, 1 in the extra columns of every H row
+#pragma unroll
+        for (int l = 0; l <= kLMax; ++l) {
+          if (l > L) break;
+          float* row = hrow<W>(a, l, p) + W;
+          *reinterpret_cast<f32x4*>(row) = f32x4{x0, x1, x2, 1.0f};
+#pragma unroll
+          for (int c = 4; c < 16; c += 4) *reinterpret_cast<f32x4*>(row + c) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+      }
     }
 
     float fpart = 0.0f, gx0 = 0.0f, gx1 = 0.0f, gx2 = 0.0f;
@@ -124,6 +154,8 @@ sdf_k32(const KArgs a) {
               s4[i] = sg;
             }
             Rout[m] = r4;
+            if constexpr (TRAIN)
+              if (valid) *reinterpret_cast<f32x4*>(hrow<W>(a, l, p) + 16 * m + 4 * g) = r4 * a.inv_kappa;
             if (!last) {
               if constexpr (MODE != MODE_QUERY) sstk[(l - 1) * kLayerStride + m * 64] = s4;
             } else {
@@ -133,7 +165,7 @@ sdf_k32(const KArgs a) {
               if constexpr (MODE != MODE_QUERY) {
                 const f32x4 wb = *reinterpret_cast<const f32x4*>(&sm[SL.wob() + 16 * m + 4 * g]);
                 const f32x4 d = wb * s4;
-                if (at_skip) {
+                if (!TRAIN && at_skip) {
 #pragma unroll
                   for (int i = 0; i < 4; ++i) {
                     const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[SL.skg() + 4 * (16 * m + 4 * g + i)]);
@@ -153,9 +185,36 @@ sdf_k32(const KArgs a) {
       for (int m = 0; m < MT; ++m) Rin[m] = Rout[m];
     }
 
+    float f = sum_lane_groups(fpart) + a.bo;
+    if constexpr (TRAIN) {
+      // clamped L1: dLoss/df = sign(clamp(f) - clamp(s)) [-delta <= f <= delta] / n
+      float u = 0.0f, lp = 0.0f;
+      if (valid) {
+        const float s = a.target[p];
+        const float cf = __builtin_fminf(__builtin_fmaxf(f, -a.delta), a.delta);
+        const float cs = __builtin_fminf(__builtin_fmaxf(s, -a.delta), a.delta);
+        const float r = cf - cs;
+        lp = __builtin_fabsf(r) * a.inv_n;
+        if (f >= -a.delta && f <= a.delta) u = (r > 0.0f ? a.inv_n : (r < 0.0f ? -a.inv_n : 0.0f));
+        if (g == 0) {
+          a.ws_loss[p] = lp;
+          float* urow = a.ws_U + 16 * p;
+          *reinterpret_cast<f32x4*>(urow) = f32x4{u, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int c = 4; c < 16; c += 4) *reinterpret_cast<f32x4*>(urow + c) = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < MT; ++m) Din[m] = Din[m] * u;  // seed d_L = u w_o sigma_L
+    }
+
     if constexpr (MODE != MODE_QUERY) {
       for (int l = L; l >= 2; --l) {
         const bool to_skip = (l - 1 == skip), to_input = (l == 2);
+        if constexpr (TRAIN)
+          if (valid)
+#pragma unroll
+            for (int m = 0; m < MT; ++m) *reinterpret_cast<f32x4*>(erow<W>(a, l, p) + 16 * m + 4 * g) = Din[m];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
           chunk_acquire<G>(gc, nch, a.stream, ring0, wave, lane);
@@ -181,7 +240,7 @@ sdf_k32(const KArgs a) {
             for (int h = 0; h < 2; ++h) {
               const int m = mt + h;
               const f32x4 d = acc[h] * s[h];
-              if (to_skip || to_input) {
+              if (!TRAIN && (to_skip || to_input)) {
                 const int off = to_input ? SL.l1g() : SL.skg();
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -199,20 +258,26 @@ sdf_k32(const KArgs a) {
 #pragma unroll
         for (int m = 0; m < MT; ++m) Din[m] = Dout[m];
       }
+      if constexpr (TRAIN)
+        if (valid)
+#pragma unroll
+          for (int m = 0; m < MT; ++m) *reinterpret_cast<f32x4*>(erow<W>(a, 1, p) + 16 * m + 4 * g) = Din[m];
     }
 
-    const float f = sum_lane_groups(fpart) + a.bo;
-    if constexpr (MODE != MODE_QUERY) {
-      gx0 = sum_lane_groups(gx0);
-      gx1 = sum_lane_groups(gx1);
-      gx2 = sum_lane_groups(gx2);
+    if constexpr (!TRAIN) {
+      if constexpr (MODE != MODE_QUERY) {
+        gx0 = sum_lane_groups(gx0);
+        gx1 = sum_lane_groups(gx1);
+        gx2 = sum_lane_groups(gx2);
+      }
+      store_outputs<MODE>(a, p, valid && g == 0, f, gx0, gx1, gx2, x0, x1, x2);
     }
-    store_outputs<MODE>(a, p, valid && g == 0, f, gx0, gx1, gx2, x0, x1, x2);
   }
 }
 
 #define SDF_K32_INST(W, MODE) template __global__ void sdf_k32<W, MODE>(const KArgs);
-#define SDF_K32_MODES(W) SDF_K32_INST(W, MODE_QUERY) SDF_K32_INST(W, MODE_GRAD) SDF_K32_INST(W, MODE_PROJECT)
+#define SDF_K32_MODES(W) SDF_K32_INST(W, MODE_QUERY) SDF_K32_INST(W, MODE_GRAD) SDF_K32_INST(W, MODE_PROJECT) \
+  SDF_K32_INST(W, MODE_TRAIN)
 SDF_K32_MODES(64)
 SDF_K32_MODES(128)
 SDF_K32_MODES(256)

@@ -1,0 +1,169 @@
+// sdf_train.hip -- device kernels of one fitting step of the neural SDF
+// (Sec. 3.1: an MLP regressed onto sampled signed distances with an L1
+// loss, clamped to [-delta, delta]).
+//
+// A step over a batch runs, chunk by chunk:
+//   pack:   the flat FP32 parameters -> FP32 MFMA fragment stream + small block
+//           (the parameters change every step, so they are packed on device);
+//   tile:   sdf_k32<W, MODE_TRAIN>: forward, dLoss/df, reverse sweep; writes
+//           h_l and e_l = dLoss/dz_l of every point of the chunk;
+//   wgrad:  grad += sum_p e_l(p) [h_{l-1}(p), x(p), 1]^T for every layer and
+//           the output layer, on v_mfma_f32_16x16x4_f32;
+//   loss:   loss += sum_p |clamp(f_p) - clamp(s_p)| / n.
+// Each output element is owned by one thread of one workgroup and chunks run
+// in stream order, so the result does not depend on scheduling.
+#include "sdf_device.hpp"
+
+namespace sdfc {
+
+// params -> FP32 fragment stream (same order as the host packer: forward
+// layers 2..L then reverse layers L..2; fragment (mt, m), lane 16g+row,
+// element i holds A[16mt + row][16m + 4g + i]) and the small FP32 block.
+__global__ void __launch_bounds__(256) pack_fp32_kernel(TrainNet t, const float* __restrict__ P,
+                                                        float* __restrict__ stream,
+                                                        float* __restrict__ small) {
+  const int W = t.W, L = t.L, MT = W / 16;
+  const int64_t per_layer = (int64_t)MT * MT * 64 * 4;
+  const int64_t total = 2 * (int64_t)(L - 1) * per_layer;
+  const SmallLayout SL{W};
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total + W;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    if (idx < total) {
+      const int64_t layer_id = idx / per_layer;
+      int64_t r = idx % per_layer;
+      const int i = (int)(r & 3);
+      const int lane = (int)((r >> 2) & 63);
+      r >>= 8;
+      const int m = (int)(r % MT), mt = (int)(r / MT);
+      const int pass = (int)(layer_id / (L - 1)), s = (int)(layer_id % (L - 1));
+      const int l = pass == 0 ? 2 + s : L - s;
+      const int row = 16 * mt + (lane & 15), col = 16 * m + 4 * (lane >> 4) + i;
+      const int K = t.K(l);
+      const float* Wl = P + t.offW[l];
+      stream[idx] = pass == 0 ? Wl[(int64_t)row * K + col] : Wl[(int64_t)col * K + row];
+    } else {
+      const int j = (int)(idx - total);
+      const float kap = t.kappa;
+      const float* w1 = P + t.offW[1] + 3 * j;
+      for (int c = 0; c < 3; ++c) {
+        small[SL.l1() + 4 * j + c] = kap * w1[c];
+        small[SL.l1g() + 4 * j + c] = w1[c];
+        float sf = 0.0f, sg = 0.0f;
+        if (t.skip) {
+          const float ws = P[t.offW[t.skip] + (int64_t)j * t.K(t.skip) + W + c];
+          sf = kap * ws;
+          sg = ws;
+        }
+        small[SL.skf() + 4 * j + c] = sf;
+        small[SL.skg() + 4 * j + c] = sg;
+      }
+      small[SL.l1() + 4 * j + 3] = kap * P[t.offb[1] + j];
+      small[SL.l1g() + 4 * j + 3] = 0.0f;
+      small[SL.skf() + 4 * j + 3] = 0.0f;
+      small[SL.skg() + 4 * j + 3] = 0.0f;
+      small[SL.wof() + j] = P[t.offo + j] / kap;
+      small[SL.wob() + j] = P[t.offo + j];
+      for (int l = 2; l <= kLMax; ++l) small[SL.bias(l) + j] = l <= L ? kap * P[t.offb[l] + j] : 0.0f;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_kernel(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// loss += sum of the chunk's per-point terms, one workgroup, fixed order.
+__global__ void __launch_bounds__(256) loss_reduce_kernel(const float* __restrict__ terms, int64_t n,
+                                                          float* __restrict__ loss) {
+  __shared__ float part[256];
+  float s = 0.0f;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += terms[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] += part[0];
+}
+
+// grad += sum_p E[p][rows] (x) H[p][cols] for one (layer, row block, column
+// block) work item.  Hidden layer l (1..L): E = e_l [n][W], H = H_{l-1}
+// [n][W+16] whose columns are h_{l-1} (W), x, y, z, 1, zeros.  Output layer
+// (l = L+1): E = dLoss/df [n][16] (row 0), H = H_L.  Columns map to
+// dW_l (hidden and skip x-columns), db_l (the "1" column), dw_o and db_o.
+__global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __restrict__ E,
+                                                    const float* __restrict__ H,
+                                                    const float* __restrict__ U, int64_t n,
+                                                    float* __restrict__ grad) {
+  const int W = t.W, L = t.L;
+  const int RB = W / 64, CB = W / 64 + 1;  // row blocks of 64; column blocks of 64 + the 16-wide tail
+  // decode the work item
+  int item = blockIdx.x;
+  int l, rb, cb;
+  if (item < RB) {  // layer 1: tail columns only
+    l = 1;
+    rb = item;
+    cb = CB - 1;
+  } else if ((item -= RB) < (L - 1) * RB * CB) {
+    l = 2 + item / (RB * CB);
+    rb = (item / CB) % RB;
+    cb = item % CB;
+  } else {
+    item -= (L - 1) * RB * CB;
+    l = L + 1;
+    rb = 0;
+    cb = item;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  const bool out_layer = (l == L + 1);
+  const bool tail = (cb == CB - 1);
+  const int ncb = tail ? 1 : 4;  // N-tiles of 16 in this block
+  const int col0 = tail ? W : 64 * cb;
+  // rows of this wave: 16 per wave (the output layer has one real row: wave 0)
+  if (out_layer && wave > 0) return;
+  const int row0 = 64 * rb + 16 * wave;
+  const float* Eb = out_layer ? U : E + (size_t)(l - 1) * n * W;
+  const int es = out_layer ? 16 : W;
+  const float* Hb = H + (size_t)(l - 1) * n * (W + 16);
+  const int hs = W + 16;
+  f32x4 acc[4] = {};
+  for (int64_t p0 = 0; p0 < n; p0 += 4) {
+    const int64_t p = p0 + g;
+    const bool ok = p < n;
+    const float a = ok ? Eb[p * es + (out_layer ? c16 : row0 + c16)] : 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      if (nt < ncb) {
+        const float b = ok ? Hb[p * hs + col0 + 16 * nt + c16] : 0.0f;
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[nt], 0, 0, 0);
+      }
+    }
+  }
+  // acc[nt][i] = sum_p E[p][row0 + 4g + i] H[p][col0 + 16 nt + c16]
+  for (int nt = 0; nt < ncb; ++nt) {
+    const int k = col0 + 16 * nt + c16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = (out_layer ? 0 : row0) + 4 * g + i;
+      const float v = acc[nt][i];
+      int64_t dst = -1;
+      if (out_layer) {
+        if (j == 0) dst = (k < W) ? t.offo + k : (k == W + 3 ? t.offo + W : -1);
+      } else if (k < W) {
+        dst = t.offW[l] + (int64_t)j * t.K(l) + k;  // hidden input columns (l >= 2)
+      } else if (k < W + 3) {
+        const int c = k - W;
+        if (l == 1) dst = t.offW[1] + 3 * j + c;
+        else if (l == t.skip) dst = t.offW[l] + (int64_t)j * t.K(l) + W + c;
+      } else if (k == W + 3) {
+        dst = t.offb[l] + j;
+      }
+      if (dst >= 0) grad[dst] += v;
+    }
+  }
+}
+
+}  // namespace sdfc

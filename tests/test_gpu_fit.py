@@ -1,0 +1,108 @@
+"""GPU parity of the fitting step (sdf_train_step) against the FP64 oracle's
+clamped-L1 loss and parameter gradient, plus determinism and a short fit."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_01614_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+B = pytest.importorskip("paper_2110_01614_amd.binding")
+
+
+def targets_sphere(x, r=0.3):
+    return (np.linalg.norm(x.astype(np.float64), axis=1) - r).astype(np.float32)
+
+
+def away_from_kinks(spec, params, pts, tgt, delta, margin=1e-4):
+    """Drop points whose FP64 f lies within margin of a kink of the clamped L1
+    loss (f = s, |f| = delta): there the FP32 and FP64 sides may legitimately
+    take different branches."""
+    f = oracle.mlp_eval(spec, params, pts, grad=False)
+    keep = (np.abs(f - tgt) > margin) & (np.abs(np.abs(f) - delta) > margin)
+    return pts[keep], tgt[keep]
+
+
+def gpu_step(spec, params, pts, tgt, delta):
+    fit = B.SdfFit(spec, len(pts))
+    P = torch.from_numpy(params).cuda()
+    loss, grad = fit.step(P, torch.from_numpy(pts).cuda(), torch.from_numpy(tgt).cuda(), delta)
+    torch.cuda.synchronize()
+    return float(loss.cpu()[0]), grad.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("widths,skip,init", [((64, 64, 64), 0, "geo"), ((128,) * 4, 2, "geo"),
+                                              ((256,) * 8, 5, "geo"), ((256,) * 8, 5, "normal")])
+def test_train_step_matches_fp64_oracle(widths, skip, init):
+    spec = I.NetSpec(widths, skip)
+    params = I.init_geometric(spec, 3) if init == "geo" else I.init_normal(spec, 3)
+    pts = I.uniform_points(3000, 17)
+    tgt = targets_sphere(pts)
+    delta = 0.1
+    pts, tgt = away_from_kinks(spec, params, pts, tgt, delta)
+    loss_ref, g_ref = oracle.fit_loss(spec, params, pts, tgt, delta)
+    loss, g = gpu_step(spec, params, pts, tgt, delta)
+    scale = np.abs(g_ref).max()
+    err = np.abs(g - g_ref)
+    print("fit %s: loss %.6g vs %.6g, max|dg| %.3e (scale %.3e)" % (widths, loss, loss_ref, err.max(), scale))
+    assert abs(loss - loss_ref) <= 1e-6 * max(1.0, abs(loss_ref))
+    # FP32 arithmetic over 3000 points: every component within 2e-5 of the largest one
+    assert err.max() <= 2e-5 * scale
+
+
+def test_train_step_chunks_and_ragged_tail():
+    """70001 points: two chunks (65536 + 4465) and a ragged last tile."""
+    spec = I.NetSpec((64, 64, 64), 0)
+    params = I.init_geometric(spec, 4)
+    pts = I.uniform_points(70001, 18)
+    tgt = targets_sphere(pts, 0.5)
+    pts, tgt = away_from_kinks(spec, params, pts, tgt, 0.1)
+    pts, tgt = np.ascontiguousarray(pts), np.ascontiguousarray(tgt)
+    assert len(pts) > 65536
+    loss_ref, g_ref = oracle.fit_loss(spec, params, pts, tgt, 0.1)
+    loss, g = gpu_step(spec, params, pts, tgt, 0.1)
+    assert abs(loss - loss_ref) <= 1e-5 * max(1.0, abs(loss_ref))
+    assert np.abs(g - g_ref).max() <= 5e-5 * np.abs(g_ref).max()
+
+
+def test_train_step_is_deterministic_and_n0():
+    spec = I.NetSpec((256,) * 8, 5)
+    params = torch.from_numpy(I.init_geometric(spec, 5)).cuda()
+    pts = torch.from_numpy(I.uniform_points(20000, 19)).cuda()
+    tgt = torch.from_numpy(targets_sphere(pts.cpu().numpy())).cuda()
+    fit = B.SdfFit(spec, 20000)
+    l1, g1 = fit.step(params, pts, tgt)
+    l2, g2 = fit.step(params, pts, tgt)
+    torch.cuda.synchronize()
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+    l0, g0 = fit.step(params, pts[:0], tgt[:0])
+    torch.cuda.synchronize()
+    assert float(l0[0]) == 0.0 and float(g0.abs().max()) == 0.0
+
+
+def test_fitting_reduces_the_loss_on_a_displaced_icosphere():
+    """A short Adam run through the autograd wrapper on brute-force targets."""
+    V, F = I.displaced_icosphere(level=3, seed=3)
+    pts = I.training_samples(V, F, 16384, seed=4)
+    tgt = oracle.mesh_sdf(V, F, pts).astype(np.float32)
+    spec = I.NetSpec((128,) * 4, 2)
+    P = torch.from_numpy(I.init_geometric(spec, 0)).cuda().requires_grad_(True)
+    X, S = torch.from_numpy(pts).cuda(), torch.from_numpy(tgt).cuda()
+    fit = B.SdfFit(spec, len(pts))
+    opt = torch.optim.Adam([P], lr=1e-3)
+    losses = []
+    for it in range(150):
+        opt.zero_grad()
+        loss = B.fit_loss(fit, P, X, S, 0.1)
+        loss.backward()
+        opt.step()
+        losses.append(float(loss))
+    print("fit loss %.4g -> %.4g" % (losses[0], losses[-1]))
+    assert losses[-1] < 0.5 * losses[0]

@@ -63,6 +63,36 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 3}), flush=True)
 
 
+def traffic_record(copy_fetch, copy_write, k_fetch, k_write, kernel, precision, out, copy_mib=256):
+    """Turn four rocprofv3 --pmc counter CSVs (FETCH_SIZE and WRITE_SIZE of the
+    copy probe and of the bench) into the traffic record: the kernel's KiB per
+    dispatch scaled by (copy bytes / copy counter), so that a counter that sees
+    only part of the memory channels is corrected by a copy of known size."""
+    import csv
+
+    def per_dispatch(path, name, counter):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if name in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        if not vals:
+            raise SystemExit("no %s rows for %r in %s" % (counter, name, path))
+        return float(np.median(vals)), len(vals)
+
+    copy_bytes = copy_mib * (1 << 20)
+    cf, _ = per_dispatch(copy_fetch, "copyBuffer", "FETCH_SIZE")
+    cw, _ = per_dispatch(copy_write, "copyBuffer", "WRITE_SIZE")
+    kf, nf = per_dispatch(k_fetch, kernel, "FETCH_SIZE")
+    kw, nw = per_dispatch(k_write, kernel, "WRITE_SIZE")
+    ff, fw = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    rec = {"kernel": kernel, "precision": precision, "source_hash": kernel_source_hash(),
+           "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
+           "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": ff, "write_scale": fw,
+           "bytes_per_launch": kf * 1024 * ff + kw * 1024 * fw}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def flops_per_point(spec) -> int:
     """Algorithmic work of forward + one reverse sweep: 4 * sum_l K_l * width_l
     (every multiply-add of every affine map, counted twice for the two sweeps)."""
@@ -92,6 +122,47 @@ def time_steps(net, X, eps, steps, warmup, torch):
     wall = time.perf_counter() - t0
     per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]  # ms, one launch each
     return wall, per
+
+
+def colliders(torch, B, I, steps, precision="bf16"):
+    """Several colliders (16 networks of widths 128-512, depths 4-8, 4M cloth
+    vertices in patches of uneven size): one grouped launch per width class,
+    against one call per network, and thirty grouped passes in one HIP graph."""
+    cs = I.collider_set()
+    eps = 0.005
+    nets = [B.SdfNet(c["spec"], c["params"], precision) for c in cs]
+    X = [torch.from_numpy(c["points"]).cuda() for c in cs]
+    n = sum(len(c["points"]) for c in cs)
+    flops = sum(flops_per_point(c["spec"]) * len(c["points"]) for c in cs)
+    grp = B.SdfGroup(nets, X, eps)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms_group = timed(grp.collide_project, steps)
+    ms_single = timed(lambda: [net.collide_project(x, eps, want=()) for net, x in zip(nets, X)], steps)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(30):
+            grp.collide_project()
+    ms_graph = timed(graph.replay, max(1, steps // 10)) / 30
+    del graph
+    grp.close()
+    for net in nets:
+        net.close()
+    return {"workload": "16 colliders, widths 128/256/512, depths 4-8, %d vertices, seed 5" % n,
+            "precision": precision, "points": n,
+            "grouped_ms": ms_group, "per_network_ms": ms_single, "graph_30_passes_ms_per_pass": ms_graph,
+            "grouped_points_per_s": n / (ms_group * 1e-3), "grouped_tflops": flops / (ms_group * 1e-3) / 1e12}
 
 
 def accuracy(spec, params, pts, net, torch, n=4096, eps=0.005):
@@ -136,11 +207,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-group", action="store_true", help="skip the several-collider measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
+    ap.add_argument("--copy-mib", type=int, default=256, help="size of the copy probe the counters saw")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("COPY_FETCH", "COPY_WRITE", "FETCH", "WRITE"),
+                    help="only write the traffic record from four rocprofv3 --pmc counter CSVs and exit")
     args = ap.parse_args()
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
+        return
+    if args.traffic_from:
+        traffic_record(*args.traffic_from, kernel="sdf_k16<256, %d, 2>" % {"bf16": 1, "fp16": 2, "bf16x3": 3}[
+            args.precision], precision=args.precision, out=TRAFFIC_FILE,
+            copy_mib=args.copy_mib)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the collision path shards across GPUs with no exchange "
@@ -177,6 +257,7 @@ def main():
         net.close()
         del X
 
+    group = None if args.no_group else colliders(torch, B, I, args.steps)
     head = results[args.precision]
     out = {
         "metric": "SDF+normal queries/s at 1M pts, BF16 vs FP32, at stated error; MFMA util %",
@@ -206,6 +287,8 @@ def main():
         "paper_context": "Table 1 / abstract: ~1M queries in ~300 ms on a Tesla T4 (TensorFlow, "
                          "Fourier features + 4 or 8 FC x 256, ReLU)",
     }
+    if group:
+        out["colliders"] = group
     if "fp32" in results:
         out["speedup_vs_fp32"] = head["points_per_s"] / results["fp32"]["points_per_s"]
     if not args.no_cpu_baseline:

@@ -19,7 +19,8 @@
  *  - Return value: SDF_OK (0) or a negative SDF_E* code.  Argument checks run
  *    on the host before anything is launched; on failure nothing is launched
  *    and sdf_last_error() (thread-local) describes the problem.
- *  - n == 0 returns SDF_OK and launches nothing.
+ *  - n == 0 returns SDF_OK and launches nothing; the array pointers may then
+ *    be NULL.
  *  - Numerical policy: outputs are float32 whatever the internal precision; a
  *    NaN f is not a hit; |grad f| == 0 gives N = 0 and the vertex is not
  *    moved; a vertex that is not moved keeps its exact bit pattern.
@@ -59,8 +60,9 @@ enum { SDF_FP32 = 0, SDF_BF16 = 1, SDF_FP16 = 2, SDF_BF16X3 = 3 };
  * Hidden layer l (1-based) has width[l-1] units and softplus activation
  * softplus_beta(z) = log(1 + exp(beta z)) / beta.  If skip_layer = s > 0,
  * hidden layer s takes [h_{s-1}; x] (hidden features first, then x, y, z).
- * This build has kernels for equal hidden widths of 64, 128 or 256, depth
- * 2..8, skip 0 or 2..depth; other shapes return SDF_EUNSUPPORTED. */
+ * This build has kernels for equal hidden widths of 64, 128, 256 or 512 (512:
+ * 16-bit precisions only), depth 2..8, skip 0 or 2..depth; other shapes
+ * return SDF_EUNSUPPORTED. */
 typedef struct {
   int32_t n_hidden;
   int32_t width[SDF_MAX_HIDDEN];
@@ -106,6 +108,28 @@ int sdf_query_grad(const sdf_net* net, const float* pts, int64_t n, float* sdf, 
  * outputs (NULL to skip) that must not overlap pts.  eps must be finite. */
 int collide_project(const sdf_net* net, float* pts, int64_t n, float eps, float* sdf,
                     float* normal, uint8_t* hit, void* stream);
+
+/* ---- several colliders per call (one network per rigid object, Sec. 3.1) ---- */
+
+typedef struct sdf_group sdf_group; /* opaque; device tables of a fixed set of calls */
+
+/* Binds n_nets networks (same device, same 16-bit precision; widths may
+ * differ) to their vertex buffers pts[i] (device float32 [counts[i]][3]) and
+ * the contact offset eps, for repeated in-place collide_project passes over
+ * all of them.  Buffers and counts are fixed for the life of the group, so a
+ * pass can be captured into a HIP graph and replayed.  Allocates its device
+ * tables here.  Errors: SDF_EINVAL, SDF_EUNSUPPORTED (FP32 networks),
+ * SDF_ENOMEM, SDF_EDEVICE. */
+int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts,
+                     const int64_t* counts, float eps, sdf_group** out);
+
+/* One collide_project pass over every (network, vertex buffer) pair of the
+ * group: one kernel launch per hidden width present, every workgroup taking
+ * one tile of one network (deeper networks' tiles first).  No allocation. */
+int sdf_group_collide_project(const sdf_group* grp, void* stream);
+
+/* Frees the group's device tables (not the networks or buffers). */
+int sdf_group_destroy(sdf_group* grp);
 
 /* ---- fitting (Sec. 3.1): MLP regressed onto sampled signed distances ---- */
 

@@ -56,6 +56,13 @@ def _load():
     lib.collide_project.argtypes = [vp, vp, i64, f32, vp, vp, vp, vp]
     lib.sdf_last_error.restype = ctypes.c_char_p
     lib.sdf_last_error.argtypes = []
+    lib.sdf_group_create.restype = ctypes.c_int
+    lib.sdf_group_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp),
+                                     ctypes.POINTER(i64), f32, ctypes.POINTER(vp)]
+    lib.sdf_group_collide_project.restype = ctypes.c_int
+    lib.sdf_group_collide_project.argtypes = [vp, vp]
+    lib.sdf_group_destroy.restype = ctypes.c_int
+    lib.sdf_group_destroy.argtypes = [vp]
     lib.sdf_train_workspace_bytes.restype = i64
     lib.sdf_train_workspace_bytes.argtypes = [desc_p, i64]
     lib.sdf_train_step.restype = ctypes.c_int
@@ -254,3 +261,48 @@ def fit_loss(fit: SdfFit, params, pts, target, delta=0.1):
             return gout * grad
 
     return _FitLoss.apply(params)
+
+
+# ------------------------------------------------------------ grouped calls
+
+def sdf_group_create(handles, pts_ptrs, counts, eps):
+    n = len(handles)
+    H = (ctypes.c_void_p * n)(*handles)
+    P = (ctypes.c_void_p * n)(*pts_ptrs)
+    C = (ctypes.c_int64 * n)(*counts)
+    g = ctypes.c_void_p()
+    _check(lib.sdf_group_create(H, n, P, C, float(eps), ctypes.byref(g)))
+    return g.value
+
+
+def sdf_group_collide_project(group, stream=None):
+    return _check(lib.sdf_group_collide_project(group, _stream(stream)))
+
+
+def sdf_group_destroy(group):
+    return _check(lib.sdf_group_destroy(group))
+
+
+class SdfGroup:
+    """A fixed set of (network, vertex tensor) pairs projected in one pass."""
+
+    def __init__(self, nets, pts_list, eps):
+        for p in pts_list:
+            SdfNet._pts(p)
+        self.nets, self.pts = list(nets), list(pts_list)
+        self.handle = sdf_group_create([n.handle for n in self.nets], [p.data_ptr() for p in self.pts],
+                                       [p.shape[0] for p in self.pts], eps)
+
+    def collide_project(self, stream=None):
+        sdf_group_collide_project(self.handle, stream)
+
+    def close(self):
+        if self.handle:
+            sdf_group_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

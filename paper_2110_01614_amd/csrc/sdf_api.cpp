@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -15,6 +16,8 @@
 namespace sdfc {
 template <int W, int PREC, int MODE>
 __global__ void sdf_k16(const KArgs a);
+template <int W, int PREC, int MODE>
+__global__ void sdf_k16_group(const KArgs* nets, const int* tile_start, int n_nets, int tile0);
 template <int W, int MODE>
 __global__ void sdf_k32(const KArgs a);
 __global__ void pack_fp32_kernel(TrainNet t, const float* P, float* stream, float* small);
@@ -74,7 +77,10 @@ int check_desc(const sdf_net_desc* d, int* W, int* L, int* skip) {
 int check_supported(int W, const sdf_net_desc* d) {
   for (int i = 1; i < d->n_hidden; ++i)
     if (d->width[i] != W) return fail(SDF_EUNSUPPORTED, "hidden widths must be equal");
-  if (W != 64 && W != 128 && W != 256) return fail(SDF_EUNSUPPORTED, "width must be 64, 128 or 256");
+  if (W != 64 && W != 128 && W != 256 && W != 512)
+    return fail(SDF_EUNSUPPORTED, "width must be 64, 128, 256 or 512");
+  if (W == 512 && d->precision == SDF_FP32)
+    return fail(SDF_EUNSUPPORTED, "width 512 has 16-bit kernels only (BF16, FP16, BF16X3)");
   if (d->n_hidden < 2 || d->n_hidden > kLMax) return fail(SDF_EUNSUPPORTED, "depth must be in [2, 8]");
   return SDF_OK;
 }
@@ -349,15 +355,29 @@ hipError_t launch(const sdf_net* net, const KArgs& a, hipStream_t s) {
     K32(64) K32(128) K32(256)
 #undef K32
   } else {
-    const int pts = (net->prec == SDF_BF16X3) ? 32 : 64;  // points per workgroup
-    dim3 grid((unsigned)((a.n + pts - 1) / pts));
+    const bool pair = net->prec == SDF_BF16X3;  // points per workgroup, as in the kernel
+    const int64_t pts = 16 * (W == 512 ? (pair ? 1 : 2) : (pair ? 2 : 4));
     dim3 block16(W >= 128 ? 512 : 256);  // 8 waves (2 per SIMD) from width 128 up
+    // a dispatch holds fewer than 2^32 work-items: split very large batches
+    const int64_t max_pts = ((int64_t)1 << 22) * pts;
+    for (int64_t p0 = 0; p0 < a.n; p0 += max_pts) {
+      KArgs c = a;
+      c.n = std::min<int64_t>(max_pts, a.n - p0);
+      c.pts_in = a.pts_in + 3 * p0;
+      c.pts_out = a.pts_out + 3 * p0;
+      if (a.sdf) c.sdf = a.sdf + p0;
+      if (a.grad) c.grad = a.grad + 3 * p0;
+      if (a.normal) c.normal = a.normal + 3 * p0;
+      if (a.hit) c.hit = a.hit + p0;
+      dim3 grid((unsigned)((c.n + pts - 1) / pts));
 #define K16(WW, PP) \
-  if (W == WW && net->prec == PP) hipLaunchKernelGGL((sdf_k16<WW, PP, MODE>), grid, block16, 0, s, a);
-    K16(64, PREC_BF16) K16(128, PREC_BF16) K16(256, PREC_BF16)
-    K16(64, PREC_FP16) K16(128, PREC_FP16) K16(256, PREC_FP16)
-    K16(64, PREC_BF16X3) K16(128, PREC_BF16X3) K16(256, PREC_BF16X3)
+  if (W == WW && net->prec == PP) hipLaunchKernelGGL((sdf_k16<WW, PP, MODE>), grid, block16, 0, s, c);
+      K16(64, PREC_BF16) K16(128, PREC_BF16) K16(256, PREC_BF16)
+      K16(64, PREC_FP16) K16(128, PREC_FP16) K16(256, PREC_FP16)
+      K16(64, PREC_BF16X3) K16(128, PREC_BF16X3) K16(256, PREC_BF16X3)
+      K16(512, PREC_BF16) K16(512, PREC_FP16) K16(512, PREC_BF16X3)
 #undef K16
+    }
   }
   return hipGetLastError();
 }
@@ -371,10 +391,11 @@ int run(const sdf_net* net, const float* pts_in, float* pts_out, int64_t n, floa
   g_err.clear();
   if (!net) return fail(SDF_EINVAL, "net is NULL");
   if (n < 0) return fail(SDF_EINVAL, "n < 0");
+  if (MODE == MODE_PROJECT && !std::isfinite(eps)) return fail(SDF_EINVAL, "eps must be finite");
+  if (n == 0) return SDF_OK;  // pointers may be NULL for an empty batch
   if (!pts_in) return fail(SDF_EINVAL, "pts is NULL");
   if (MODE == MODE_QUERY && !sdf) return fail(SDF_EINVAL, "sdf is NULL");
   if (MODE == MODE_GRAD && !grad) return fail(SDF_EINVAL, "grad is NULL");
-  if (MODE == MODE_PROJECT && !std::isfinite(eps)) return fail(SDF_EINVAL, "eps must be finite");
   if (!aligned4(pts_in) || !aligned4(sdf) || !aligned4(grad) || !aligned4(normal))
     return fail(SDF_EINVAL, "float arrays must be 4-byte aligned");
   if (n > ((int64_t)1 << 40)) return fail(SDF_EINVAL, "n too large");
@@ -556,6 +577,7 @@ int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* p
   a.ws_H = (float*)(ws + lay.H);
   a.ws_U = (float*)(ws + lay.U);
   a.ws_loss = (float*)(ws + lay.loss);
+  a.bo_dev = params + t.offo + W;
   a.delta = delta;
   a.inv_n = (float)(1.0 / (double)n);
   a.inv_kappa = 1.0f / t.kappa;
@@ -576,6 +598,155 @@ int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* p
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, s, a.ws_loss, cn, loss);
   }
   const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SDF_OK : hip_fail(e, "kernel launch");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ grouped calls
+
+struct sdf_group {
+  int device = 0;
+  int prec = 0;
+  struct Class {
+    int W = 0, n = 0, tiles = 0;
+    KArgs* d_args = nullptr;  // [n]
+    int* d_start = nullptr;   // [n]
+  };
+  std::vector<Class> classes;
+  void* d_mem = nullptr;
+};
+
+extern "C" {
+
+int sdf_group_destroy(sdf_group* grp) {
+  if (!grp) return SDF_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(grp->device);
+  if (grp->d_mem) (void)hipFree(grp->d_mem);
+  (void)hipSetDevice(prev);
+  delete grp;
+  return SDF_OK;
+}
+
+int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, const int64_t* counts,
+                     float eps, sdf_group** out) {
+  g_err.clear();
+  if (!out) return fail(SDF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!nets || !pts || !counts || n_nets < 1 || n_nets > 4096)
+    return fail(SDF_EINVAL, "need 1..4096 networks with vertex buffers and counts");
+  if (!std::isfinite(eps)) return fail(SDF_EINVAL, "eps must be finite");
+  const int dev = nets[0] ? nets[0]->device : 0;
+  const int prec = nets[0] ? nets[0]->prec : 0;
+  for (int i = 0; i < n_nets; ++i) {
+    if (!nets[i]) return fail(SDF_EINVAL, "a network handle is NULL");
+    if (nets[i]->device != dev) return fail(SDF_EINVAL, "all networks must live on one device");
+    if (nets[i]->prec != prec) return fail(SDF_EINVAL, "all networks must share one precision");
+    if (counts[i] < 0 || counts[i] > ((int64_t)1 << 31)) return fail(SDF_EINVAL, "bad vertex count");
+    if (counts[i] > 0 && (!pts[i] || !aligned4(pts[i]))) return fail(SDF_EINVAL, "bad vertex buffer");
+  }
+  if (prec == SDF_FP32) return fail(SDF_EUNSUPPORTED, "grouped launches run the 16-bit kernels only");
+  const bool pair = prec == SDF_BF16X3;
+  auto pts_per_tile = [&](int W) { return 16 * (W == 512 ? (pair ? 1 : 2) : (pair ? 2 : 4)); };
+
+  sdf_group* grp = new sdf_group();
+  grp->device = dev;
+  grp->prec = prec;
+  std::vector<KArgs> args;
+  std::vector<int> starts;
+  const int widths[4] = {64, 128, 256, 512};
+  for (int W : widths) {
+    std::vector<int> idx;
+    for (int i = 0; i < n_nets; ++i)
+      if (nets[i]->W == W && counts[i] > 0) idx.push_back(i);
+    if (idx.empty()) continue;
+    // longest tiles first (deeper networks, then larger patches)
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+      if (nets[a]->L != nets[b]->L) return nets[a]->L > nets[b]->L;
+      return counts[a] > counts[b];
+    });
+    sdf_group::Class c;
+    c.W = W;
+    c.n = (int)idx.size();
+    int64_t tiles = 0;
+    for (int i : idx) {
+      const sdf_net* net = nets[i];
+      KArgs a{};
+      a.pts_in = pts[i];
+      a.pts_out = pts[i];
+      a.n = counts[i];
+      a.eps = eps;
+      a.bo = net->bo;
+      a.stream = net->d_stream;
+      a.small = net->d_small;
+      a.L = net->L;
+      a.skip = net->skip;
+      starts.push_back((int)tiles);
+      args.push_back(a);
+      tiles += (counts[i] + pts_per_tile(W) - 1) / pts_per_tile(W);
+    }
+    if (tiles > 0x7fffffff) {
+      sdf_group_destroy(grp);
+      return fail(SDF_EINVAL, "too many tiles");
+    }
+    c.tiles = (int)tiles;
+    grp->classes.push_back(c);
+  }
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(dev);
+  const size_t abytes = args.size() * sizeof(KArgs), sbytes = starts.size() * sizeof(int);
+  if (!args.empty()) {
+    if (hipMalloc(&grp->d_mem, abytes + sbytes + 256) != hipSuccess) {
+      (void)hipSetDevice(prev);
+      sdf_group_destroy(grp);
+      return fail(SDF_ENOMEM, "hipMalloc(group tables)");
+    }
+    unsigned char* m = (unsigned char*)grp->d_mem;
+    if (hipMemcpy(m, args.data(), abytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m + abytes, starts.data(), sbytes, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipSetDevice(prev);
+      sdf_group_destroy(grp);
+      return fail(SDF_EDEVICE, "hipMemcpy(group tables)");
+    }
+    int off = 0;
+    for (auto& c : grp->classes) {
+      c.d_args = (KArgs*)m + off;
+      c.d_start = (int*)(m + abytes) + off;
+      off += c.n;
+    }
+  }
+  (void)hipSetDevice(prev);
+  *out = grp;
+  return SDF_OK;
+}
+
+int sdf_group_collide_project(const sdf_group* grp, void* stream) {
+  g_err.clear();
+  if (!grp) return fail(SDF_EINVAL, "group is NULL");
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  if (prev != grp->device) (void)hipSetDevice(grp->device);
+  const hipStream_t s = (hipStream_t)stream;
+  for (const auto& c : grp->classes) {
+    const dim3 block(c.W >= 128 ? 512 : 256);
+    // a dispatch holds fewer than 2^32 work-items
+    for (int64_t t0 = 0; t0 < c.tiles; t0 += 1 << 22) {
+      const dim3 grid((unsigned)std::min<int64_t>(1 << 22, c.tiles - t0));
+#define KG(WW, PP)                                                                                  \
+  if (c.W == WW && grp->prec == PP)                                                                 \
+    hipLaunchKernelGGL((sdf_k16_group<WW, PP, MODE_PROJECT>), grid, block, 0, s, c.d_args, c.d_start, \
+                       c.n, (int)t0);
+      KG(64, PREC_BF16) KG(128, PREC_BF16) KG(256, PREC_BF16) KG(512, PREC_BF16)
+      KG(64, PREC_FP16) KG(128, PREC_FP16) KG(256, PREC_FP16) KG(512, PREC_FP16)
+      KG(64, PREC_BF16X3) KG(128, PREC_BF16X3) KG(256, PREC_BF16X3) KG(512, PREC_BF16X3)
+#undef KG
+    }
+  }
+  const hipError_t e = hipGetLastError();
+  if (prev != grp->device) (void)hipSetDevice(prev);
   return e == hipSuccess ? SDF_OK : hip_fail(e, "kernel launch");
 }
 

@@ -38,6 +38,7 @@ struct KArgs {
   int ntiles;            // ceil(n / 64)
   // fitting (MODE_TRAIN) only: per-point targets and the per-chunk workspace
   const float* target;   // [n] signed distances
+  const float* bo_dev;   // output bias in device memory (the flat parameters)
   float* ws_E;           // [L][n][W]: dLoss/dz_l per point
   float* ws_H;           // [L+1][n][W+16]: h_l, then x, y, z, 1, zeros (h_0 slot: x, y, z, 1 only)
   float* ws_U;           // [n][16]: dLoss/df, zeros

@@ -33,16 +33,18 @@ namespace sdfc {
 template <int W, int NS>
 struct GeoB {
   static constexpr int NWV = W >= 128 ? 8 : 4;  // waves per workgroup (2 per SIMD when 8)
-  static constexpr int NCT = NS == 1 ? 4 : 2;  // column tiles (16 points each)
+  // column tiles (16 points each): fewer at width 512 and for BF16 pairs, so
+  // that the reverse-sweep stack of a wave fits its registers
+  static constexpr int NCT = W == 512 ? (NS == 1 ? 2 : 1) : (NS == 1 ? 4 : 2);
   static constexpr int PTS = 16 * NCT;         // points per workgroup
   static constexpr int FW = W / NWV;           // features per wave
   static constexpr int MTW = FW / 16;          // M-tiles per wave
   static constexpr int KB = W / 32;            // K-blocks of 32 per layer
-  static constexpr int DMAX = NS == 2 ? 2 : SDF_K16_D;
+  static constexpr int DMAX = W == 512 ? 1 : (NS == 2 ? 2 : SDF_K16_D);
   static constexpr int D = KB < DMAX ? KB : DMAX;  // weight prefetch depth in K-steps
   // r_1..r_LS of the stack live in LDS (the reverse sweep reads them last);
   // the rest stay in registers.
-  static constexpr int LS = W == 256 ? 1 : 0;
+  static constexpr int LS = W >= 256 ? 1 : 0;
   static constexpr int STK_BYTES = (LS > 0 ? LS : 1) * NWV * MTW * NCT * NS * 64 * 8;
   static constexpr int WAVE_BYTES = KB * MTW * NS * kFrag;  // one wave's slice of a layer
   static constexpr int LAYER_BYTES = NWV * WAVE_BYTES;
@@ -84,9 +86,10 @@ __device__ __forceinline__ void split4(f32x4 v, uint2& hi, uint2& lo) {
   lo = pack4<PREC_BF16>(v - h);
 }
 
+// The whole per-workgroup pass over tile `tile` (points [tile PTS, tile PTS +
+// PTS) of a.pts_in) of network `a`.
 template <int W, int PREC, int MODE>
-__global__ void __attribute__((amdgpu_flat_work_group_size(64 * (W >= 128 ? 8 : 4), 64 * (W >= 128 ? 8 : 4))))
-sdf_k16(const KArgs a) {
+__device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   constexpr int NS = PREC == PREC_BF16X3 ? 2 : 1;
   constexpr int OP = PREC == PREC_BF16X3 ? PREC_BF16 : PREC;  // MFMA operand type
   using G = GeoB<W, NS>;
@@ -105,7 +108,7 @@ sdf_k16(const KArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, col = lane & 15;
   const int L = a.L, skip = a.skip;
-  const int64_t base = (int64_t)blockIdx.x * PTS;
+  const int64_t base = (int64_t)tile * PTS;
   const unsigned char* fwd = a.stream;  // layers 2..L, LAYER_BYTES each
   const unsigned char* rev = a.stream + (size_t)(L - 1) * G::LAYER_BYTES;  // layers L..2
 
@@ -409,8 +412,32 @@ sdf_k16(const KArgs a) {
   }
 }
 
+#define K16_WG_SIZE(W) __attribute__((amdgpu_flat_work_group_size(64 * (W >= 128 ? 8 : 4), 64 * (W >= 128 ? 8 : 4))))
+
+template <int W, int PREC, int MODE>
+__global__ void K16_WG_SIZE(W) sdf_k16(const KArgs a) {
+  k16_tile<W, PREC, MODE>(a, blockIdx.x);
+}
+
+// Several networks of one width in one launch: workgroup b runs tile
+// b - tile_start[i] of network i, where tile_start[i] <= b < tile_start[i+1].
+template <int W, int PREC, int MODE>
+__global__ void K16_WG_SIZE(W) sdf_k16_group(const KArgs* __restrict__ nets,
+                                             const int* __restrict__ tile_start, int n_nets,
+                                             int tile0) {
+  const int b = tile0 + (int)blockIdx.x;
+  int lo = 0, hi = n_nets - 1;  // last i with tile_start[i] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const int i = __builtin_amdgcn_readfirstlane(lo);
+  k16_tile<W, PREC, MODE>(nets[i], b - tile_start[i]);
+}
+
 #define SDF_K16_INST(W, PREC, MODE) \
-  template __global__ void sdf_k16<W, PREC, MODE>(const KArgs);
+  template __global__ void sdf_k16<W, PREC, MODE>(const KArgs); \
+  template __global__ void sdf_k16_group<W, PREC, MODE>(const KArgs*, const int*, int, int);
 #define SDF_K16_MODES(W, PREC) \
   SDF_K16_INST(W, PREC, MODE_QUERY) SDF_K16_INST(W, PREC, MODE_GRAD) SDF_K16_INST(W, PREC, MODE_PROJECT)
 #define SDF_K16_PRECS(W) \
@@ -418,5 +445,6 @@ sdf_k16(const KArgs a) {
 SDF_K16_PRECS(64)
 SDF_K16_PRECS(128)
 SDF_K16_PRECS(256)
+SDF_K16_PRECS(512)
 
 }  // namespace sdfc

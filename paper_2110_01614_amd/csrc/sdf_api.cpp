@@ -222,7 +222,7 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
     // [wave][K-block][local M-tile][part] fragments: each wave reads one
     // contiguous slice holding the rows it owns (features [w W/4, (w+1) W/4)).
     // BF16x3 stores every weight as a pair hi = bf16(v), lo = bf16(v - hi).
-    const int NWV = W >= 128 ? 8 : 4;  // waves per workgroup, as in the kernel
+    const int NWV = k16_waves(W);
     const int KB = W / 32, MTW = W / (16 * NWV), NS = (prec == SDF_BF16X3) ? 2 : 1;
     for (int w = 0; w < NWV; ++w)
       for (int kb = 0; kb < KB; ++kb)
@@ -356,8 +356,8 @@ hipError_t launch(const sdf_net* net, const KArgs& a, hipStream_t s) {
 #undef K32
   } else {
     const bool pair = net->prec == SDF_BF16X3;  // points per workgroup, as in the kernel
-    const int64_t pts = 16 * (W == 512 ? (pair ? 1 : 2) : (pair ? 2 : 4));
-    dim3 block16(W >= 128 ? 512 : 256);  // 8 waves (2 per SIMD) from width 128 up
+    const int64_t pts = k16_points(W, pair ? 2 : 1);
+    dim3 block16(64 * k16_waves(W));
     // a dispatch holds fewer than 2^32 work-items: split very large batches
     const int64_t max_pts = ((int64_t)1 << 22) * pts;
     for (int64_t p0 = 0; p0 < a.n; p0 += max_pts) {
@@ -649,7 +649,7 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
   }
   if (prec == SDF_FP32) return fail(SDF_EUNSUPPORTED, "grouped launches run the 16-bit kernels only");
   const bool pair = prec == SDF_BF16X3;
-  auto pts_per_tile = [&](int W) { return 16 * (W == 512 ? (pair ? 1 : 2) : (pair ? 2 : 4)); };
+  auto pts_per_tile = [&](int W) { return k16_points(W, pair ? 2 : 1); };
 
   sdf_group* grp = new sdf_group();
   grp->device = dev;
@@ -731,7 +731,7 @@ int sdf_group_collide_project(const sdf_group* grp, void* stream) {
   if (prev != grp->device) (void)hipSetDevice(grp->device);
   const hipStream_t s = (hipStream_t)stream;
   for (const auto& c : grp->classes) {
-    const dim3 block(c.W >= 128 ? 512 : 256);
+    const dim3 block(64 * k16_waves(c.W));
     // a dispatch holds fewer than 2^32 work-items
     for (int64_t t0 = 0; t0 < c.tiles; t0 += 1 << 22) {
       const dim3 grid((unsigned)std::min<int64_t>(1 << 22, c.tiles - t0));

@@ -1,28 +1,34 @@
 // sdf_k16.hip -- fused neural-SDF query / gradient / collision kernel with
 // 16-bit (BF16 or FP16) MFMA operands and FP32 accumulation, for gfx950.
 //
-// One workgroup = 4 wave64 = 64 points (4 column tiles of 16).  The hidden
-// features of every layer are split across the waves: wave w owns features
-// [w W/4, (w+1) W/4) for all 64 points.  Per hidden layer l >= 2 each wave
-// computes its rows of z_l = W_l r_{l-1} with v_mfma_f32_16x16x32_{bf16,f16}:
-// A = its own weight fragments, loaded straight from L2 into registers (each
-// weight byte enters the CU once per workgroup), B = the previous layer's
-// activations of all features, read from an LDS exchange buffer that every
-// wave fills with its own rows (Sec. 3.1, Eq. 1).  The reverse sweep of
-// Sec. 3.2 runs the same way over W_l^T: a wave owns the input-feature rows
-// it produced in the forward pass, so the sigmoids it needs come from its own
-// registers (1 - 2^{-r}, r stored as 16-bit).  Layer 1 (K = 3), the skip
-// x-columns, the output layer, the normal (Eq. 2) and the move to the contact
-// point (Eq. 3) are FP32 VALU; per-point sums across waves go through LDS.
+// One workgroup takes a tile of points (64 for widths up to 256: 4 column
+// tiles of 16) through the whole network.  The hidden features of every layer
+// are split across the waves (8 waves from width 128, i.e. 2 per SIMD; 4
+// below): wave w owns features [w W/NWV, (w+1) W/NWV) for all points of the
+// tile.  Per hidden layer l >= 2 each wave computes its rows of
+// z_l = W_l r_{l-1} with v_mfma_f32_16x16x32_{bf16,f16}: A = its own weight
+// fragments, loaded straight from L2 into registers (each weight byte enters
+// the CU once per tile), B = the previous layer's activations of all
+// features, read from an LDS exchange buffer that every wave fills with its
+// own rows (Sec. 3.1, Eq. 1).  The reverse sweep of Sec. 3.2 runs the same way
+// over W_l^T: a wave owns the input-feature rows it produced in the forward
+// pass, so the sigmoids it needs come from its own registers (1 - 2^{-r}, r
+// stored as 16-bit).  Layer 1 (K = 3), the skip x-columns, the output layer,
+// the normal (Eq. 2) and the move to the contact point (Eq. 3) are FP32 VALU;
+// per-point sums across waves go through LDS.  One workgroup barrier per
+// layer publishes the exchange buffer; at width 256 a wave's own rows form a
+// whole K-block of the next contraction, whose MFMAs are issued from
+// registers before that barrier.
 #include <type_traits>
 
 #include "sdf_device.hpp"
 
 #ifndef SDF_K16_D
-#define SDF_K16_D 2
+#define SDF_K16_D 1
 #endif
-#ifndef SDF_K16_BDB
-#define SDF_K16_BDB 1
+
+#ifndef SDF_K16_OWN
+#define SDF_K16_OWN 1
 #endif
 
 namespace sdfc {
@@ -32,10 +38,8 @@ namespace sdfc {
 // which keeps about 16 significant bits (compensated "BF16x3").
 template <int W, int NS>
 struct GeoB {
-  static constexpr int NWV = W >= 128 ? 8 : 4;  // waves per workgroup (2 per SIMD when 8)
-  // column tiles (16 points each): fewer at width 512 and for BF16 pairs, so
-  // that the reverse-sweep stack of a wave fits its registers
-  static constexpr int NCT = W == 512 ? (NS == 1 ? 2 : 1) : (NS == 1 ? 4 : 2);
+  static constexpr int NWV = k16_waves(W);    // waves per workgroup
+  static constexpr int NCT = k16_cols(W, NS);  // column tiles of 16 points
   static constexpr int PTS = 16 * NCT;         // points per workgroup
   static constexpr int FW = W / NWV;           // features per wave
   static constexpr int MTW = FW / 16;          // M-tiles per wave
@@ -126,15 +130,6 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   for (int i = tid; i < SL.floats() / 4; i += NT)
     reinterpret_cast<f32x4*>(sm)[i] = reinterpret_cast<const f32x4*>(a.small)[i];
 
-  // first weight fragments (forward layer 2)
-  u32x4 Aq[D][MTW][NS];
-#pragma unroll
-  for (int s = 0; s < D; ++s)
-#pragma unroll
-    for (int mt = 0; mt < MTW; ++mt)
-#pragma unroll
-      for (int ps = 0; ps < NS; ++ps) Aq[s][mt][ps] = *wfrag<G>(fwd, wave, s, mt, ps, lane);
-  __syncthreads();
 
   // feature index of (local M-tile mt, lane group g, element i)
   auto feat = [&](int mt, int i) { return 16 * (MTW * wave + mt) + 4 * g + i; };
@@ -143,9 +138,47 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     const int m = MTW * wave + mt;
     return ((m >> 1) * NCT + ct) * kFrag + lane * 16 + 8 * (m & 1);
   };
-  uint2 stk[kLMax][MTW][NCT][NS];  // r_l of the wave's rows, l = LS+1..L-1 (registers)
+  // The wave's rows cover whole K-blocks of the next contraction when MTW is
+  // even: K-block kb0 + j holds local M-tiles 2j, 2j + 1 (see act_off).
+  constexpr int NOWN = (SDF_K16_OWN && NS == 1 && W != 512 && MTW % 2 == 0) ? MTW / 2 : 0;
+  const int kb0 = wave * NOWN;
+  u32x4 ownB[NOWN > 0 ? NOWN : 1][NCT][NS];
+
+  // first weight fragments (forward layer 2), in the wave's K-block order
+  u32x4 Aq[D][MTW][NS];
+#pragma unroll
+  for (int s = 0; s < D; ++s)
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+      for (int ps = 0; ps < NS; ++ps) Aq[s][mt][ps] = *wfrag<G>(fwd, wave, (kb0 + s) & (KB - 1), mt, ps, lane);
+  __syncthreads();
+
+  // r_l of the wave's rows, l = LS+1..L-1, in registers: as the operand tuples
+  // of the wave's own K-blocks (stq, NOWN > 0) or per M-tile (stk).
+  u32x4 stq[kLMax][NOWN > 0 ? NOWN : 1][NCT][NS];
+  uint2 stk[kLMax][MTW][NCT][NS];
   auto stk_at = [&](int l, int mt, int ct, int ps) -> uint2& {
     return stk_lds[(((((l - 1) * NWV + wave) * MTW + mt) * NCT + ct) * NS + ps) * 64 + lane];
+  };
+  auto keep_own = [&](int l) {  // after layer l's epilogue: stack the own tuples
+    if constexpr (NOWN > 0)
+      if (l > G::LS)
+#pragma unroll
+        for (int j = 0; j < NOWN; ++j)
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int ps = 0; ps < NS; ++ps) stq[l][j][ct][ps] = ownB[j][ct][ps];
+  };
+  auto stacked = [&](int l, int mt, int ct, int ps) -> uint2 {
+    if (l <= G::LS) return stk_at(l, mt, ct, ps);
+    if constexpr (NOWN > 0) {
+      const u32x4 q = stq[l][mt / 2][ct][ps];
+      return (mt & 1) ? uint2{q[2], q[3]} : uint2{q[0], q[1]};
+    } else {
+      return stk[l][mt][ct][ps];
+    }
   };
   // Store v (FP32) as the wave's operand rows: 16-bit (NS = 1) or a BF16 pair.
   // keep_l: stack layer to record v in (0: none).
@@ -158,9 +191,13 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
 #pragma unroll
     for (int ps = 0; ps < NS; ++ps) {
       *reinterpret_cast<uint2*>(out + ps * G::ACT_BYTES + act_off(mt, ct)) = p[ps];
+      if constexpr (NOWN > 0) {
+        ownB[mt / 2][ct][ps][2 * (mt & 1)] = p[ps].x;
+        ownB[mt / 2][ct][ps][2 * (mt & 1) + 1] = p[ps].y;
+      }
       if (keep_l > 0 && keep_l <= G::LS)
         stk_at(keep_l, mt, ct, ps) = p[ps];
-      else if (keep_l > G::LS)
+      else if (NOWN == 0 && keep_l > G::LS)
         stk[keep_l][mt][ct][ps] = p[ps];
     }
   };
@@ -192,47 +229,36 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
       put(&act[0][0][0], mt, ct, r, 1);
     }
   }
-  lds_barrier();
+  keep_own(1);
 
-  // One hidden layer's contraction for this wave: acc[mt][ct] += A(mt, kb) B(kb, ct)
-  // with B from exchange buffer `in`; prefetches the next layer's first D K-steps
-  // from `next` (nullptr: nothing follows).
+  // One hidden layer's contraction for this wave: acc[mt][ct] += A(mt, kb) B(kb, ct).
+  // The K-blocks are taken in the order kb0, kb0 + 1, ... (mod KB).  When the
+  // wave's own rows form whole K-blocks (OWN), those come first, straight from
+  // the registers `put` filled, and are issued before the workgroup barrier
+  // that publishes the other waves' rows, so they run while the barrier
+  // resolves and the first LDS reads are in flight.  The next layer's first D
+  // weight K-steps are prefetched from `next` (nullptr: nothing follows).
   auto contract = [&](f32x4 (&acc)[MTW][NCT], const unsigned char* in, const unsigned char* layer,
                       const unsigned char* next) {
-    constexpr int NB = SDF_K16_BDB ? 2 : 1;
-    u32x4 Bv[NB][NCT][NS];  // B operands of K-steps kb (in use) and kb + 1 (in flight)
-    auto loadB = [&](u32x4 (&dst)[NCT][NS], int kb) {
-#pragma unroll
-      for (int ct = 0; ct < NCT; ++ct)
-#pragma unroll
-        for (int ps = 0; ps < NS; ++ps)
-          dst[ct][ps] = *reinterpret_cast<const u32x4*>(in + ps * G::ACT_BYTES + (kb * NCT + ct) * kFrag + lane * 16);
-    };
-    if (NB == 2) loadB(Bv[0], 0);
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      if (NB == 1)
-        loadB(Bv[0], kb);
-      else if (kb + 1 < KB)
-        loadB(Bv[(kb + 1) % NB], kb + 1);
+    auto kbi = [&](int j) { return (kb0 + j) & (KB - 1); };
+    auto step = [&](int j, const u32x4 (&B)[NCT][NS]) {
       u32x4 Acur[MTW][NS];
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-        for (int ps = 0; ps < NS; ++ps) Acur[mt][ps] = Aq[kb % D][mt][ps];
-      const int nk = kb + D;
+        for (int ps = 0; ps < NS; ++ps) Acur[mt][ps] = Aq[j % D][mt][ps];
+      const int nk = j + D;
       if (nk < KB) {
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-          for (int ps = 0; ps < NS; ++ps) Aq[kb % D][mt][ps] = *wfrag<G>(layer, wave, nk, mt, ps, lane);
+          for (int ps = 0; ps < NS; ++ps) Aq[j % D][mt][ps] = *wfrag<G>(layer, wave, kbi(nk), mt, ps, lane);
       } else if (next) {
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-          for (int ps = 0; ps < NS; ++ps) Aq[kb % D][mt][ps] = *wfrag<G>(next, wave, nk - KB, mt, ps, lane);
+          for (int ps = 0; ps < NS; ++ps) Aq[j % D][mt][ps] = *wfrag<G>(next, wave, kbi(nk - KB), mt, ps, lane);
       }
-      const auto& B = Bv[kb % NB];
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
@@ -243,6 +269,23 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
           }
           acc[mt][ct] = mfma16<OP>(Acur[mt][0], B[ct][0], acc[mt][ct]);
         }
+    };
+#pragma unroll
+    for (int j = 0; j < NOWN; ++j) step(j, ownB[j]);
+    lds_barrier();
+    u32x4 Bv[2][NCT][NS];  // B operands of K-steps j (in use) and j + 1 (in flight)
+    auto loadB = [&](u32x4 (&dst)[NCT][NS], int j) {
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int ps = 0; ps < NS; ++ps)
+          dst[ct][ps] = *reinterpret_cast<const u32x4*>(in + ps * G::ACT_BYTES + (kbi(j) * NCT + ct) * kFrag + lane * 16);
+    };
+    loadB(Bv[0], NOWN);
+#pragma unroll
+    for (int j = NOWN; j < KB; ++j) {
+      if (j + 1 < KB) loadB(Bv[(j + 1 - NOWN) & 1], j + 1);
+      step(j, Bv[(j - NOWN) & 1]);
     }
   };
 
@@ -287,6 +330,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
           for (int i = 0; i < 4; ++i) r[i] = softplus2(acc[mt][ct][i]);
           put(out, mt, ct, r, l);
         }
+      keep_own(l);
     } else {
       // output layer f = (w_o/kappa) . r_L and the reverse-sweep seed
       // d_L = w_o (1 - 2^-r_L); SKIPG: layer L is also the skip layer.
@@ -332,7 +376,6 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
       else
         last_epi(std::false_type{});
     }
-    lds_barrier();
   }
 
   // ---- reverse sweep over W_l^T, l = L..2 ----
@@ -369,8 +412,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
           for (int ct = 0; ct < NCT; ++ct) {
             uint2 q[NS];
 #pragma unroll
-            for (int ps = 0; ps < NS; ++ps)
-              q[ps] = (l - 1 <= G::LS) ? stk_at(l - 1, mt, ct, ps) : stk[l - 1][mt][ct][ps];
+            for (int ps = 0; ps < NS; ++ps) q[ps] = stacked(l - 1, mt, ct, ps);
             f32x4 r = unpack4<OP>(q[0]);
             if constexpr (NS == 2) r += unpack4<OP>(q[1]);
             f32x4 d;
@@ -396,7 +438,6 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
         bwd_epi(std::true_type{});
       else
         bwd_epi(std::false_type{});
-      if (l > 2) lds_barrier();
     }
   }
 
@@ -412,7 +453,8 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   }
 }
 
-#define K16_WG_SIZE(W) __attribute__((amdgpu_flat_work_group_size(64 * (W >= 128 ? 8 : 4), 64 * (W >= 128 ? 8 : 4))))
+#define K16_WG_SIZE(W) \
+  __attribute__((amdgpu_flat_work_group_size(64 * k16_waves(W), 64 * k16_waves(W)), amdgpu_waves_per_eu(2)))
 
 template <int W, int PREC, int MODE>
 __global__ void K16_WG_SIZE(W) sdf_k16(const KArgs a) {

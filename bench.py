@@ -23,7 +23,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "fp32": 157.3}  # MI355X dense MFMA
+PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "fp8": 5000.0, "fp32": 157.3}  # MI355X dense MFMA
 KERNEL_SOURCES = ["paper_2110_01614_amd/csrc/sdf_k16.hip", "paper_2110_01614_amd/csrc/sdf_device.hpp",
                   "paper_2110_01614_amd/csrc/sdf_layout.hpp", "paper_2110_01614_amd/csrc/sdf_api.cpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sdf_k16_cloth1m.json")
@@ -165,6 +165,29 @@ def colliders(torch, B, I, steps, precision="bf16"):
             "grouped_points_per_s": n / (ms_group * 1e-3), "grouped_tflops": flops / (ms_group * 1e-3) / 1e12}
 
 
+def precision_study(torch, B, I, steps):
+    """3->512x8->1 skip 5 on 4M uniform points (geometric init): BF16, BF16x3
+    and FP8 operands, time per collide_project pass and error against FP64."""
+    spec, params, pts, eps = I.workload_inputs("wide4m")
+    n = len(pts)
+    fpp = flops_per_point(spec)
+    X0 = torch.from_numpy(pts).cuda()
+    out = {"workload": "wide4m: 3->512x8->1, skip 5, geometric init seed 0, %d uniform points seed 1" % n,
+           "flops_per_point": fpp}
+    for prec in ("bf16", "bf16x3", "fp8"):
+        net = B.SdfNet(spec, params, prec)
+        X = X0.clone()
+        wall, per = time_steps(net, X, eps, steps, 2, torch)
+        ms = float(np.mean(per))
+        tf = fpp * n / (ms * 1e-3) / 1e12
+        out[prec] = {"kernel_ms_mean": ms, "points_per_s": n / (ms * 1e-3), "tflops": tf,
+                     "mfma_frac": tf / PEAK_TFLOPS[prec],
+                     "accuracy_vs_fp64": accuracy(spec, params, pts, net, torch, n=1024)}
+        net.close()
+        del X
+    return out
+
+
 def accuracy(spec, params, pts, net, torch, n=4096, eps=0.005):
     import oracle
     idx = np.random.default_rng(3).choice(len(pts), n, replace=False)
@@ -203,11 +226,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "bf16x3", "fp32"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "bf16x3", "fp8", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-group", action="store_true", help="skip the several-collider measurement")
+    ap.add_argument("--no-study", action="store_true", help="skip the 512-wide precision study")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     ap.add_argument("--copy-mib", type=int, default=256, help="size of the copy probe the counters saw")
@@ -240,7 +264,7 @@ def main():
     X0 = torch.from_numpy(pts).cuda()
     results = {}
     order = [args.precision] + ([] if args.no_compare else
-                                [p for p in ("fp32", "fp16", "bf16x3", "bf16") if p != args.precision])
+                                [p for p in ("fp32", "fp16", "bf16x3", "fp8", "bf16") if p != args.precision])
     for prec in order:
         net = B.SdfNet(spec, params, prec)
         X = X0.clone()
@@ -253,11 +277,17 @@ def main():
         r["mfma_frac"] = r["tflops"] / PEAK_TFLOPS[prec]
         if not args.no_accuracy:
             r["accuracy_vs_fp64"] = accuracy(spec, params, pts, net, torch)
+            # the same shape with the geometric (SDF-like) initialisation
+            pg = I.workload_inputs("cloth1m", n=1, init="geometric")[1]
+            ng = B.SdfNet(spec, pg, prec)
+            r["accuracy_vs_fp64_geometric_init"] = accuracy(spec, pg, pts, ng, torch, n=2048)
+            ng.close()
         results[prec] = r
         net.close()
         del X
 
     group = None if args.no_group else colliders(torch, B, I, args.steps)
+    study = None if args.no_study else precision_study(torch, B, I, max(3, args.steps // 4))
     head = results[args.precision]
     out = {
         "metric": "SDF+normal queries/s at 1M pts, BF16 vs FP32, at stated error; MFMA util %",
@@ -289,6 +319,8 @@ def main():
     }
     if group:
         out["colliders"] = group
+    if study:
+        out["precision_study_512"] = study
     if "fp32" in results:
         out["speedup_vs_fp32"] = head["points_per_s"] / results["fp32"]["points_per_s"]
     if not args.no_cpu_baseline:

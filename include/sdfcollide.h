@@ -50,9 +50,15 @@ enum {
  * SDF_BF16X3 carries every operand (weights, activations, back-propagated
  * errors) as a BF16 pair hi + lo and forms each product as hi*hi + lo*hi +
  * hi*lo: three BF16 MFMAs per product, about 16 significant bits.
+ * SDF_FP8 uses OCP E4M3 operands (3 mantissa bits) on the K = 128 FP8 MFMA:
+ * every layer's weights carry a power-of-two scale chosen at sdf_net_create
+ * from the largest weight (largest scaled weight in (224, 448]), activations
+ * enter as softplus output * beta * log2(e) / 4 and back-propagated errors
+ * with the per-layer scales of the 16-bit paths, all saturated at +-448; the
+ * stored activations of the reverse sweep stay BF16.  Widths 128-512.
  * Layer 1 (K = 3), the skip x-columns, the output layer, the normalisation
  * and the projection always run in FP32. */
-enum { SDF_FP32 = 0, SDF_BF16 = 1, SDF_FP16 = 2, SDF_BF16X3 = 3 };
+enum { SDF_FP32 = 0, SDF_BF16 = 1, SDF_FP16 = 2, SDF_BF16X3 = 3, SDF_FP8 = 4 };
 
 #define SDF_MAX_HIDDEN 16
 
@@ -61,8 +67,8 @@ enum { SDF_FP32 = 0, SDF_BF16 = 1, SDF_FP16 = 2, SDF_BF16X3 = 3 };
  * softplus_beta(z) = log(1 + exp(beta z)) / beta.  If skip_layer = s > 0,
  * hidden layer s takes [h_{s-1}; x] (hidden features first, then x, y, z).
  * This build has kernels for equal hidden widths of 64, 128, 256 or 512 (512:
- * 16-bit precisions only), depth 2..8, skip 0 or 2..depth; other shapes
- * return SDF_EUNSUPPORTED. */
+ * 16-bit and FP8 precisions only; FP8: 128 and up), depth 2..8, skip 0 or
+ * 2..depth; other shapes return SDF_EUNSUPPORTED. */
 typedef struct {
   int32_t n_hidden;
   int32_t width[SDF_MAX_HIDDEN];
@@ -113,7 +119,7 @@ int collide_project(const sdf_net* net, float* pts, int64_t n, float eps, float*
 
 typedef struct sdf_group sdf_group; /* opaque; device tables of a fixed set of calls */
 
-/* Binds n_nets networks (same device, same 16-bit precision; widths may
+/* Binds n_nets networks (same device, same 16-bit or FP8 precision; widths may
  * differ) to their vertex buffers pts[i] (device float32 [counts[i]][3]) and
  * the contact offset eps, for repeated in-place collide_project passes over
  * all of them.  Buffers and counts are fixed for the life of the group, so a

@@ -15,9 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsdfcollide.so")
 
 SDF_OK, SDF_EINVAL, SDF_EUNSUPPORTED, SDF_ENOMEM, SDF_EDEVICE = 0, -1, -2, -3, -4
-SDF_FP32, SDF_BF16, SDF_FP16, SDF_BF16X3 = 0, 1, 2, 3
+SDF_FP32, SDF_BF16, SDF_FP16, SDF_BF16X3, SDF_FP8 = 0, 1, 2, 3, 4
 SDF_MAX_HIDDEN = 16
-PRECISIONS = {"fp32": SDF_FP32, "bf16": SDF_BF16, "fp16": SDF_FP16, "bf16x3": SDF_BF16X3}
+PRECISIONS = {"fp32": SDF_FP32, "bf16": SDF_BF16, "fp16": SDF_FP16, "bf16x3": SDF_BF16X3, "fp8": SDF_FP8}
 
 
 class sdf_net_desc(ctypes.Structure):

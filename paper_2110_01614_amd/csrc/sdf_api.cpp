@@ -40,6 +40,8 @@ struct sdf_net {
   float* d_small = nullptr;
   float* d_scratch = nullptr;  // FP32 sigma stack, one slot per resident workgroup
   int slots = 0;
+  float fsc[kLMax + 1] = {};  // FP8: forward / reverse operand-scale undo per layer
+  float rsc[kLMax + 1] = {};
 };
 
 namespace {
@@ -66,7 +68,7 @@ int check_desc(const sdf_net_desc* d, int* W, int* L, int* skip) {
     return fail(SDF_EINVAL, "skip_layer must be 0 or in [2, n_hidden]");
   if (!std::isfinite(d->beta) || d->beta <= 0.0f) return fail(SDF_EINVAL, "beta must be finite and > 0");
   if (d->precision != SDF_FP32 && d->precision != SDF_BF16 && d->precision != SDF_FP16 &&
-      d->precision != SDF_BF16X3)
+      d->precision != SDF_BF16X3 && d->precision != SDF_FP8)
     return fail(SDF_EINVAL, "unknown precision");
   *W = d->width[0];
   *L = d->n_hidden;
@@ -80,7 +82,9 @@ int check_supported(int W, const sdf_net_desc* d) {
   if (W != 64 && W != 128 && W != 256 && W != 512)
     return fail(SDF_EUNSUPPORTED, "width must be 64, 128, 256 or 512");
   if (W == 512 && d->precision == SDF_FP32)
-    return fail(SDF_EUNSUPPORTED, "width 512 has 16-bit kernels only (BF16, FP16, BF16X3)");
+    return fail(SDF_EUNSUPPORTED, "width 512 has 16-bit and FP8 kernels only");
+  if (W < 128 && d->precision == SDF_FP8)
+    return fail(SDF_EUNSUPPORTED, "FP8 needs width 128, 256 or 512 (K-blocks of 128)");
   if (d->n_hidden < 2 || d->n_hidden > kLMax) return fail(SDF_EUNSUPPORTED, "depth must be in [2, 8]");
   return SDF_OK;
 }
@@ -130,6 +134,42 @@ uint16_t to_bf16(float v) {  // round to nearest even
 
 uint16_t to_fp16(float v) {  // round to nearest even, saturating to +-inf on overflow
   return __builtin_bit_cast(uint16_t, (_Float16)v);
+}
+
+// float -> OCP E4M3 (bias 7, no infinities, largest finite 448), round to
+// nearest even, saturated at +-448; values below 2^-10 in magnitude -> 0.
+uint8_t to_e4m3(float v) {
+  const uint8_t sign = std::signbit(v) ? 0x80 : 0x00;
+  const double a = std::fabs((double)v);
+  if (!(a == a)) return 0x7f;  // NaN
+  if (a >= 448.0) return sign | 0x7e;
+  int e;
+  std::frexp(a, &e);  // a = m 2^e, m in [0.5, 1)
+  int ex = e - 1;     // a in [2^ex, 2^(ex+1))
+  if (ex < -6) ex = -6;  // subnormal range shares the 2^-6 exponent with a zero field
+  const double q = std::nearbyint(std::ldexp(a, 3 - ex));  // units of 2^(ex-3), ties to even
+  int mant = (int)q;
+  int field = ex + 7;
+  if (a < std::ldexp(1.0, -6)) {  // subnormal: value = mant 2^-9
+    if (mant >= 8) return sign | 0x08;  // rounded up to 2^-6
+    return sign | (uint8_t)mant;
+  }
+  if (mant >= 16) {  // rounded up to the next binade
+    mant = 8;
+    field += 1;
+  }
+  if (field > 15 || (field == 15 && mant - 8 > 6)) return sign | 0x7e;
+  return sign | (uint8_t)((field << 3) | (mant - 8));
+}
+
+// Power-of-two exponent s with max |v| 2^s in (224, 448] (0 for an all-zero set).
+int fp8_exponent(double maxabs) {
+  if (!(maxabs > 0.0)) return 0;
+  int s = (int)std::floor(std::log2(448.0 / maxabs));
+  while (std::ldexp(maxabs, s) > 448.0) --s;
+  if (s > 60) s = 60;
+  if (s < -60) s = -60;
+  return s;
 }
 
 // Per-layer power-of-two scales of the reverse-sweep vectors d_l (16-bit
@@ -192,6 +232,21 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
   const int prec = desc->precision;
   const double kappa = (double)desc->beta / std::log(2.0);  // beta * log2(e)
   std::vector<int> S = (prec == SDF_FP32) ? std::vector<int>(L + 1, 0) : reverse_scales(n);
+  // FP8: weight exponents of the forward (sf) and reverse (sr) contraction of
+  // every layer; forward activations enter the exchange as r / 4.
+  std::vector<int> sf(L + 1, 0), sr(L + 1, 0);
+  if (prec == SDF_FP8) {
+    for (int l = 2; l <= L; ++l) {
+      const int K = n.K(l);
+      double mf = 0.0;
+      for (int j = 0; j < W; ++j)
+        for (int k = 0; k < W; ++k) mf = std::max(mf, std::fabs((double)n.Wl[l][(size_t)j * K + k]));
+      sf[l] = fp8_exponent(mf);
+      sr[l] = fp8_exponent(mf * std::ldexp(1.0, S[l - 1] - S[l]));
+    }
+  }
+  // factor folded into the FP32 terms that are added to a scaled forward accumulator
+  auto facc = [&](int l) { return prec == SDF_FP8 ? std::ldexp(1.0, sf[l] - 2) : 1.0; };
 
   // ---- small FP32 block ----
   const SmallLayout SL{W};
@@ -206,13 +261,13 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
     if (skip) {
       const float* ws = n.Wl[skip] + (size_t)j * n.K(skip) + W;
       for (int c = 0; c < 3; ++c) {
-        sm[SL.skf() + 4 * j + c] = (float)(kappa * ws[c]);
+        sm[SL.skf() + 4 * j + c] = (float)(kappa * ws[c] * facc(skip));
         sm[SL.skg() + 4 * j + c] = (float)std::ldexp((double)ws[c], -S[skip]);
       }
     }
     sm[SL.wof() + j] = (float)(n.wo[j] / kappa);
     sm[SL.wob() + j] = (float)std::ldexp((double)n.wo[j], S[L]);
-    for (int l = 2; l <= L; ++l) sm[SL.bias(l) + j] = (float)(kappa * n.bl[l][j]);
+    for (int l = 2; l <= L; ++l) sm[SL.bias(l) + j] = (float)(kappa * n.bl[l][j] * facc(l));
   }
 
   // ---- fragment stream: forward W_2..W_L, then reverse W_L^T..W_2^T ----
@@ -250,6 +305,23 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
               }
             }
   };
+  auto emit8 = [&](auto at, int sexp) {
+    // [wave][K-block of 128][local M-tile] fragments of 64 lanes x 32 bytes:
+    // lane 16 g + row, byte e holds A[16 mt + row][128 kb + 16 (e / 4) + 4 g + (e % 4)],
+    // the features lane group g holds of M-tiles 8 kb .. 8 kb + 7.
+    const int NWV = k16_waves(W);
+    const int KB = W / 128, MTW = W / (16 * NWV);
+    for (int w = 0; w < NWV; ++w)
+      for (int kb = 0; kb < KB; ++kb)
+        for (int ml = 0; ml < MTW; ++ml)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int g = lane >> 4, row = lane & 15, mt = MTW * w + ml;
+            for (int e = 0; e < 32; ++e) {
+              const int col = 128 * kb + 16 * (e / 4) + 4 * g + (e % 4);
+              stream.push_back(to_e4m3((float)std::ldexp((double)at(16 * mt + row, col), sexp)));
+            }
+          }
+  };
   auto emit32 = [&](auto at) {
     const int MT = W / 16;
     for (int mt = 0; mt < MT; ++mt)
@@ -274,12 +346,14 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
       auto rev = [&](int r, int c) { return Wl[(size_t)c * K + r] * sc; };
       if (prec == SDF_FP32) {
         if (pass == 0) emit32(fwd); else emit32(rev);
+      } else if (prec == SDF_FP8) {
+        if (pass == 0) emit8(fwd, sf[l]); else emit8(rev, sr[l]);
       } else {
         if (pass == 0) emit16(fwd); else emit16(rev);
       }
     }
   }
-  if (prec != SDF_FP32) {
+  if (prec != SDF_FP32 && prec != SDF_FP8) {
     // a 16-bit value that overflowed would make every gradient through it infinite
     for (size_t i = 0; i + 1 < stream.size(); i += 2) {
       const uint16_t h = (uint16_t)(stream[i] | (stream[i + 1] << 8));
@@ -303,6 +377,10 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
   net->prec = prec;
   net->bo = n.bo;
   net->stream_bytes = stream.size();
+  for (int l = 0; l <= kLMax; ++l) {
+    net->fsc[l] = (prec == SDF_FP8 && l >= 2 && l <= L) ? (float)std::ldexp(1.0, 2 - sf[l]) : 1.0f;
+    net->rsc[l] = (prec == SDF_FP8 && l >= 2 && l <= L) ? (float)std::ldexp(1.0, -sr[l]) : 1.0f;
+  }
   net->chunks_per_layer = cpl;
   auto cleanup = [&](int code, const std::string& msg) {
     sdf_net_destroy(net);
@@ -356,7 +434,7 @@ hipError_t launch(const sdf_net* net, const KArgs& a, hipStream_t s) {
 #undef K32
   } else {
     const bool pair = net->prec == SDF_BF16X3;  // points per workgroup, as in the kernel
-    const int64_t pts = k16_points(W, pair ? 2 : 1);
+    const int64_t pts = k16_points(W, pair ? 2 : 1, net->prec == SDF_FP8);
     dim3 block16(64 * k16_waves(W));
     // a dispatch holds fewer than 2^32 work-items: split very large batches
     const int64_t max_pts = ((int64_t)1 << 22) * pts;
@@ -376,6 +454,7 @@ hipError_t launch(const sdf_net* net, const KArgs& a, hipStream_t s) {
       K16(64, PREC_FP16) K16(128, PREC_FP16) K16(256, PREC_FP16)
       K16(64, PREC_BF16X3) K16(128, PREC_BF16X3) K16(256, PREC_BF16X3)
       K16(512, PREC_BF16) K16(512, PREC_FP16) K16(512, PREC_BF16X3)
+      K16(128, PREC_FP8) K16(256, PREC_FP8) K16(512, PREC_FP8)
 #undef K16
     }
   }
@@ -415,6 +494,10 @@ int run(const sdf_net* net, const float* pts_in, float* pts_out, int64_t n, floa
   a.stream = net->d_stream;
   a.small = net->d_small;
   a.scratch = net->d_scratch;
+  for (int l = 0; l <= kLMax; ++l) {
+    a.fsc[l] = net->fsc[l];
+    a.rsc[l] = net->rsc[l];
+  }
   a.L = net->L;
   a.skip = net->skip;
   a.nch = (net->L - 1) * net->chunks_per_layer * (MODE == MODE_QUERY ? 1 : 2);
@@ -649,7 +732,7 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
   }
   if (prec == SDF_FP32) return fail(SDF_EUNSUPPORTED, "grouped launches run the 16-bit kernels only");
   const bool pair = prec == SDF_BF16X3;
-  auto pts_per_tile = [&](int W) { return k16_points(W, pair ? 2 : 1); };
+  auto pts_per_tile = [&](int W) { return k16_points(W, pair ? 2 : 1, prec == SDF_FP8); };
 
   sdf_group* grp = new sdf_group();
   grp->device = dev;
@@ -683,6 +766,10 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
       a.small = net->d_small;
       a.L = net->L;
       a.skip = net->skip;
+      for (int l = 0; l <= kLMax; ++l) {
+        a.fsc[l] = net->fsc[l];
+        a.rsc[l] = net->rsc[l];
+      }
       starts.push_back((int)tiles);
       args.push_back(a);
       tiles += (counts[i] + pts_per_tile(W) - 1) / pts_per_tile(W);
@@ -742,6 +829,7 @@ int sdf_group_collide_project(const sdf_group* grp, void* stream) {
       KG(64, PREC_BF16) KG(128, PREC_BF16) KG(256, PREC_BF16) KG(512, PREC_BF16)
       KG(64, PREC_FP16) KG(128, PREC_FP16) KG(256, PREC_FP16) KG(512, PREC_FP16)
       KG(64, PREC_BF16X3) KG(128, PREC_BF16X3) KG(256, PREC_BF16X3) KG(512, PREC_BF16X3)
+      KG(128, PREC_FP8) KG(256, PREC_FP8) KG(512, PREC_FP8)
 #undef KG
     }
   }

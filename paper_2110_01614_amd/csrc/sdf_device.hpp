@@ -10,13 +10,15 @@ namespace sdfc {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 enum { MODE_QUERY = 0, MODE_GRAD = 1, MODE_PROJECT = 2, MODE_TRAIN = 3 };
-enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2, PREC_BF16X3 = 3 };
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2, PREC_BF16X3 = 3, PREC_FP8 = 4 };
 
 // Everything a launch needs; passed by value in the kernel argument segment.
 struct KArgs {
@@ -39,6 +41,10 @@ struct KArgs {
   // fitting (MODE_TRAIN) only: per-point targets and the per-chunk workspace
   const float* target;   // [n] signed distances
   const float* bo_dev;   // output bias in device memory (the flat parameters)
+  // FP8 operands: per-layer factors that undo the power-of-two operand scales
+  // of the forward (fsc[l]) and reverse (rsc[l]) contraction of layer l
+  float fsc[kLMax + 1];
+  float rsc[kLMax + 1];
   float* ws_E;           // [L][n][W]: dLoss/dz_l per point
   float* ws_H;           // [L+1][n][W+16]: h_l, then x, y, z, 1, zeros (h_0 slot: x, y, z, 1 only)
   float* ws_U;           // [n][16]: dLoss/df, zeros
@@ -146,6 +152,22 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
   else
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
                                                   __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+// v_mfma_f32_16x16x128_f8f6f4 with E4M3 operands on both sides (no block
+// scales): 32 bytes of A and of B per lane, K = 128.
+__device__ __forceinline__ f32x4 mfma_fp8(u32x8 a, u32x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(__builtin_bit_cast(i32x8, a),
+                                                          __builtin_bit_cast(i32x8, b), c, 0, 0, 0, 0, 0, 0);
+}
+
+// Four floats as four E4M3 bytes (round to nearest even), saturated to +-448.
+__device__ __forceinline__ unsigned pack4_fp8(f32x4 v) {
+  f32x4 c;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) c[i] = __builtin_fminf(__builtin_fmaxf(v[i], -448.0f), 448.0f);
+  unsigned w = __builtin_amdgcn_cvt_pk_fp8_f32(c[0], c[1], 0u, false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(c[2], c[3], w, true);
 }
 
 __device__ __forceinline__ float sum_lane_groups(float v) {

@@ -36,25 +36,27 @@ namespace sdfc {
 // NS = 1: plain 16-bit operands.  NS = 2: every operand is carried as a BF16
 // pair hi + lo (lo = bf16(v - hi)) and each product is hi*hi + lo*hi + hi*lo,
 // which keeps about 16 significant bits (compensated "BF16x3").
-template <int W, int NS>
+template <int W, int NS, bool F8 = false>
 struct GeoB {
   static constexpr int NWV = k16_waves(W);    // waves per workgroup
-  static constexpr int NCT = k16_cols(W, NS);  // column tiles of 16 points
+  static constexpr int NCT = k16_cols(W, NS, F8);  // column tiles of 16 points
   static constexpr int PTS = 16 * NCT;         // points per workgroup
   static constexpr int FW = W / NWV;           // features per wave
   static constexpr int MTW = FW / 16;          // M-tiles per wave
-  static constexpr int KB = W / 32;            // K-blocks of 32 per layer
-  static constexpr int DMAX = W == 512 ? 1 : (NS == 2 ? 2 : SDF_K16_D);
+  static constexpr int KM = F8 ? 128 : 32;      // K per MFMA
+  static constexpr int KB = W / KM;            // K-blocks per layer
+  static constexpr int FRAG = F8 ? 2 * kFrag : kFrag;  // bytes of one operand fragment
+  static constexpr int DMAX = W == 512 ? (F8 ? 2 : 1) : (NS == 2 ? 2 : SDF_K16_D);
   static constexpr int D = KB < DMAX ? KB : DMAX;  // weight prefetch depth in K-steps
   // r_1..r_LS of the stack live in LDS (the reverse sweep reads them last);
   // the rest stay in registers.
   static constexpr int LS = W >= 256 ? 1 : 0;
   static constexpr int STK_BYTES = (LS > 0 ? LS : 1) * NWV * MTW * NCT * NS * 64 * 8;
-  static constexpr int WAVE_BYTES = KB * MTW * NS * kFrag;  // one wave's slice of a layer
+  static constexpr int WAVE_BYTES = KB * MTW * NS * FRAG;  // one wave's slice of a layer
   static constexpr int LAYER_BYTES = NWV * WAVE_BYTES;
-  static constexpr int ACT_BYTES = KB * NCT * kFrag;        // one exchange buffer part
+  static constexpr int ACT_BYTES = KB * NCT * FRAG;        // one exchange buffer part
   static constexpr int NS_ = NS;
-  static_assert(MTW >= 1 && KB % D == 0, "shape");
+  static_assert(MTW >= 1 && KB >= 1 && KB % D == 0, "shape");
 };
 
 template <int PREC>
@@ -76,11 +78,12 @@ __device__ __forceinline__ f32x4 unpack4(uint2 u) {
 }
 
 // Address of weight fragment part ps (0 hi, 1 lo) of (K-step kb, local M-tile mt).
-template <class G>
-__device__ __forceinline__ const u32x4* wfrag(const unsigned char* layer, int wave, int kb, int mt,
-                                              int ps, int lane) {
-  return reinterpret_cast<const u32x4*>(layer + (size_t)wave * G::WAVE_BYTES +
-                                        (size_t)((kb * G::MTW + mt) * G::NS_ + ps) * kFrag + lane * 16);
+template <class G, class AT>
+__device__ __forceinline__ const AT* wfrag(const unsigned char* layer, int wave, int kb, int mt, int ps,
+                                           int lane) {
+  return reinterpret_cast<const AT*>(layer + (size_t)wave * G::WAVE_BYTES +
+                                     (size_t)((kb * G::MTW + mt) * G::NS_ + ps) * G::FRAG +
+                                     lane * (int)sizeof(AT));
 }
 
 // v as a BF16 pair: hi = bf16(v), lo = bf16(v - hi).
@@ -95,8 +98,13 @@ __device__ __forceinline__ void split4(f32x4 v, uint2& hi, uint2& lo) {
 template <int W, int PREC, int MODE>
 __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   constexpr int NS = PREC == PREC_BF16X3 ? 2 : 1;
-  constexpr int OP = PREC == PREC_BF16X3 ? PREC_BF16 : PREC;  // MFMA operand type
-  using G = GeoB<W, NS>;
+  // FP8: E4M3 exchange operands (forward activations stored as r / 4), weights
+  // scaled per layer by a power of two undone by a.fsc / a.rsc; the stack of r
+  // for the reverse sweep stays BF16.
+  constexpr bool F8 = PREC == PREC_FP8;
+  constexpr int OP = (PREC == PREC_BF16X3 || F8) ? PREC_BF16 : PREC;  // 16-bit operand / stack type
+  using G = GeoB<W, NS, F8>;
+  using AT = std::conditional_t<F8, u32x8, u32x4>;  // one lane's share of an operand fragment
   constexpr int NWV = G::NWV, NT = 64 * NWV;
   constexpr SmallLayout SL{W};
   constexpr int MTW = G::MTW, KB = G::KB, NCT = G::NCT, D = G::D, PTS = G::PTS;
@@ -136,22 +144,25 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   // LDS byte offset of this lane's half-fragment for global M-tile of local mt, tile ct
   auto act_off = [&](int mt, int ct) {
     const int m = MTW * wave + mt;
-    return ((m >> 1) * NCT + ct) * kFrag + lane * 16 + 8 * (m & 1);
+    if constexpr (F8)
+      return ((m >> 3) * NCT + ct) * G::FRAG + lane * 32 + 4 * (m & 7);
+    else
+      return ((m >> 1) * NCT + ct) * kFrag + lane * 16 + 8 * (m & 1);
   };
   // The wave's rows cover whole K-blocks of the next contraction when MTW is
   // even: K-block kb0 + j holds local M-tiles 2j, 2j + 1 (see act_off).
-  constexpr int NOWN = (SDF_K16_OWN && NS == 1 && W != 512 && MTW % 2 == 0) ? MTW / 2 : 0;
+  constexpr int NOWN = (SDF_K16_OWN && NS == 1 && !F8 && W != 512 && MTW % 2 == 0) ? MTW / 2 : 0;
   const int kb0 = wave * NOWN;
   u32x4 ownB[NOWN > 0 ? NOWN : 1][NCT][NS];
 
   // first weight fragments (forward layer 2), in the wave's K-block order
-  u32x4 Aq[D][MTW][NS];
+  AT Aq[D][MTW][NS];
 #pragma unroll
   for (int s = 0; s < D; ++s)
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-      for (int ps = 0; ps < NS; ++ps) Aq[s][mt][ps] = *wfrag<G>(fwd, wave, (kb0 + s) & (KB - 1), mt, ps, lane);
+      for (int ps = 0; ps < NS; ++ps) Aq[s][mt][ps] = *wfrag<G, AT>(fwd, wave, (kb0 + s) & (KB - 1), mt, ps, lane);
   __syncthreads();
 
   // r_l of the wave's rows, l = LS+1..L-1, in registers: as the operand tuples
@@ -183,6 +194,17 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   // Store v (FP32) as the wave's operand rows: 16-bit (NS = 1) or a BF16 pair.
   // keep_l: stack layer to record v in (0: none).
   auto put = [&](unsigned char* out, int mt, int ct, f32x4 v, int keep_l) {
+    if constexpr (F8) {
+      *reinterpret_cast<unsigned*>(out + act_off(mt, ct)) = pack4_fp8(keep_l > 0 ? v * 0.25f : v);
+      if (keep_l > 0) {
+        const uint2 q = pack4<PREC_BF16>(v);
+        if (keep_l <= G::LS)
+          stk_at(keep_l, mt, ct, 0) = q;
+        else
+          stk[keep_l][mt][ct][0] = q;
+      }
+      return;
+    }
     uint2 p[NS];
     if constexpr (NS == 1)
       p[0] = pack4<OP>(v);
@@ -241,8 +263,8 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   auto contract = [&](f32x4 (&acc)[MTW][NCT], const unsigned char* in, const unsigned char* layer,
                       const unsigned char* next) {
     auto kbi = [&](int j) { return (kb0 + j) & (KB - 1); };
-    auto step = [&](int j, const u32x4 (&B)[NCT][NS]) {
-      u32x4 Acur[MTW][NS];
+    auto step = [&](int j, const AT (&B)[NCT][NS]) {
+      AT Acur[MTW][NS];
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
@@ -252,34 +274,40 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-          for (int ps = 0; ps < NS; ++ps) Aq[j % D][mt][ps] = *wfrag<G>(layer, wave, kbi(nk), mt, ps, lane);
+          for (int ps = 0; ps < NS; ++ps) Aq[j % D][mt][ps] = *wfrag<G, AT>(layer, wave, kbi(nk), mt, ps, lane);
       } else if (next) {
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-          for (int ps = 0; ps < NS; ++ps) Aq[j % D][mt][ps] = *wfrag<G>(next, wave, kbi(nk - KB), mt, ps, lane);
+          for (int ps = 0; ps < NS; ++ps) Aq[j % D][mt][ps] = *wfrag<G, AT>(next, wave, kbi(nk - KB), mt, ps, lane);
       }
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
-          if constexpr (NS == 2) {  // small cross terms first
-            acc[mt][ct] = mfma16<OP>(Acur[mt][1], B[ct][0], acc[mt][ct]);
-            acc[mt][ct] = mfma16<OP>(Acur[mt][0], B[ct][1], acc[mt][ct]);
+          if constexpr (F8) {
+            acc[mt][ct] = mfma_fp8(Acur[mt][0], B[ct][0], acc[mt][ct]);
+          } else {
+            if constexpr (NS == 2) {  // small cross terms first
+              acc[mt][ct] = mfma16<OP>(Acur[mt][1], B[ct][0], acc[mt][ct]);
+              acc[mt][ct] = mfma16<OP>(Acur[mt][0], B[ct][1], acc[mt][ct]);
+            }
+            acc[mt][ct] = mfma16<OP>(Acur[mt][0], B[ct][0], acc[mt][ct]);
           }
-          acc[mt][ct] = mfma16<OP>(Acur[mt][0], B[ct][0], acc[mt][ct]);
         }
     };
+    if constexpr (NOWN > 0)
 #pragma unroll
-    for (int j = 0; j < NOWN; ++j) step(j, ownB[j]);
+      for (int j = 0; j < NOWN; ++j) step(j, ownB[j]);
     lds_barrier();
-    u32x4 Bv[2][NCT][NS];  // B operands of K-steps j (in use) and j + 1 (in flight)
-    auto loadB = [&](u32x4 (&dst)[NCT][NS], int j) {
+    AT Bv[2][NCT][NS];  // B operands of K-steps j (in use) and j + 1 (in flight)
+    auto loadB = [&](AT (&dst)[NCT][NS], int j) {
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
         for (int ps = 0; ps < NS; ++ps)
-          dst[ct][ps] = *reinterpret_cast<const u32x4*>(in + ps * G::ACT_BYTES + (kbi(j) * NCT + ct) * kFrag + lane * 16);
+          dst[ct][ps] = *reinterpret_cast<const AT*>(in + ps * G::ACT_BYTES + (kbi(j) * NCT + ct) * G::FRAG +
+                                                     lane * (int)sizeof(AT));
     };
     loadB(Bv[0], NOWN);
 #pragma unroll
@@ -327,7 +355,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
         for (int ct = 0; ct < NCT; ++ct) {
           f32x4 r;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) r[i] = softplus2(acc[mt][ct][i]);
+          for (int i = 0; i < 4; ++i) r[i] = softplus2(F8 ? acc[mt][ct][i] * a.fsc[l] : acc[mt][ct][i]);
           put(out, mt, ct, r, l);
         }
       keep_own(l);
@@ -351,7 +379,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
             f32x4 d;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const float r = softplus2(acc[mt][ct][i]);
+              const float r = softplus2(F8 ? acc[mt][ct][i] * a.fsc[l] : acc[mt][ct][i]);
               part[ct][0] = __builtin_fmaf(wf[i], r, part[ct][0]);
               d[i] = __builtin_fmaf(-wb[i], __builtin_amdgcn_exp2f(-r), wb[i]);
             }
@@ -417,8 +445,10 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
             if constexpr (NS == 2) r += unpack4<OP>(q[1]);
             f32x4 d;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              d[i] = __builtin_fmaf(-acc[mt][ct][i], __builtin_amdgcn_exp2f(-r[i]), acc[mt][ct][i]);
+            for (int i = 0; i < 4; ++i) {
+              const float gi = F8 ? acc[mt][ct][i] * a.rsc[l] : acc[mt][ct][i];
+              d[i] = __builtin_fmaf(-gi, __builtin_amdgcn_exp2f(-r[i]), gi);
+            }
             if constexpr (decltype(TOX)::value) {
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
@@ -488,5 +518,8 @@ SDF_K16_PRECS(64)
 SDF_K16_PRECS(128)
 SDF_K16_PRECS(256)
 SDF_K16_PRECS(512)
+SDF_K16_MODES(128, PREC_FP8)
+SDF_K16_MODES(256, PREC_FP8)
+SDF_K16_MODES(512, PREC_FP8)
 
 }  // namespace sdfc

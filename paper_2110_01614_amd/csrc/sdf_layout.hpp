@@ -48,17 +48,18 @@ struct SmallLayout {
 
 // Workgroup shape of the 16-bit kernels, shared by the packer (the weight
 // stream is ordered by wave), the launcher and the kernel.  NS = 1: plain
-// 16-bit operands; NS = 2: BF16 hi/lo pairs.  Widths from 128 run 8 waves (2
-// per SIMD) on 64 points; pairs and width 512 take fewer points so that the
-// reverse-sweep stack of a wave still fits its registers.
+// 16-bit operands; NS = 2: BF16 hi/lo pairs; f8: E4M3 operands (wider
+// weight fragments).  Widths from 128 run 8 waves (2 per SIMD) on 64 points;
+// pairs, FP8 and width 512 take fewer points so that the reverse-sweep stack
+// and the operands of a wave still fit its registers.
 __host__ __device__ constexpr int k16_waves(int W) { return W >= 128 ? 8 : 4; }
 #ifndef SDF_K16_COLS256
 #define SDF_K16_COLS256 4
 #endif
-__host__ __device__ constexpr int k16_cols(int W, int NS) {
-  return W == 512 ? (NS == 1 ? 2 : 1) : (NS == 1 ? (W == 256 ? SDF_K16_COLS256 : 4) : 2);
+__host__ __device__ constexpr int k16_cols(int W, int NS, bool f8 = false) {
+  return W == 512 ? ((NS == 1 && !f8) ? 2 : 1) : (NS == 1 ? (W == 256 ? SDF_K16_COLS256 : 4) : 2);
 }
-__host__ __device__ constexpr int k16_points(int W, int NS) { return 16 * k16_cols(W, NS); }
+__host__ __device__ constexpr int k16_points(int W, int NS, bool f8 = false) { return 16 * k16_cols(W, NS, f8); }
 
 // Fragment geometry of one hidden layer.
 //  16-bit (v_mfma_f32_16x16x32_{bf16,f16}): M-tiles of 16 output rows, K-blocks

@@ -69,6 +69,21 @@ def test_unsupported_shapes_are_reported(widths):
     assert e.value.code == B.SDF_EUNSUPPORTED
 
 
+@pytest.mark.parametrize("widths,precision", [((64,) * 4, "fp8"), ((96,) * 3, "fp8"), ((512,) * 3, "fp32")])
+def test_precision_width_combinations_without_kernels(widths, precision):
+    d = B.make_desc(widths, 0, precision=precision)
+    with pytest.raises(B.SdfError) as e:
+        B.sdf_net_create(d, np.zeros(B.sdf_param_count(d), np.float32))
+    assert e.value.code == B.SDF_EUNSUPPORTED
+
+
+def test_unknown_precision_is_rejected():
+    d = B.make_desc((128,) * 3, 0)
+    d.precision = 7
+    assert B.sdf_param_count(d) == -1
+    assert "precision" in B.sdf_last_error()
+
+
 def test_null_handle_is_rejected_without_launch():
     assert B.lib.sdf_query(None, None, 5, None, None) == B.SDF_EINVAL
     assert "NULL" in B.sdf_last_error()

@@ -5,6 +5,12 @@ Tolerances:
   BF16 / FP16 operands: the stated accuracy target, |f - f64| <= 1e-3 and
   normal angle <= 1e-2 rad (max over all points), asserted where each test
   says so; the measured statistics are always printed.
+  FP8 (E4M3) operands, no target is stated; the bound comes from the
+  arithmetic: 3 mantissa bits (unit roundoff 2^-4) on both operands of every
+  hidden contraction.  A numpy model of exactly these roundings gives, on
+  well-conditioned (geometric-init) nets of widths 256-512, |f - f64| <= 0.075
+  and normal angles with p99 <= 0.08 and max <= 0.27 rad; the tests assert
+  |f - f64| <= 0.15, p99 angle <= 0.15 and max angle <= 0.6 rad there.
 Hits are decided in FP32 on both sides of the comparison that must be exact:
 the GPU's flag equals (its own f < eps); against FP64 the flags agree wherever
 |f64 - eps| exceeds the SDF tolerance.
@@ -28,7 +34,8 @@ if not torch.cuda.is_available():  # pragma: no cover - collected on CPU machines
 B = pytest.importorskip("paper_2110_01614_amd.binding")
 
 STATS = os.environ.get("SDF_STATS_OUT")
-TOL = {"fp32": (1e-5, 1e-4), "bf16": (1e-3, 1e-2), "fp16": (1e-3, 1e-2), "bf16x3": (1e-3, 1e-2)}
+TOL = {"fp32": (1e-5, 1e-4), "bf16": (1e-3, 1e-2), "fp16": (1e-3, 1e-2), "bf16x3": (1e-3, 1e-2),
+       "fp8": (0.15, 0.6)}
 # precisions whose accuracy target is asserted on every workload
 GATED = ("fp32", "bf16x3")
 
@@ -165,6 +172,53 @@ def test_cloth_full_size_sampled():
         if precision in GATED:
             assert ang.max() <= tol_a
         assert np.array_equal(got["hit"].astype(bool), got["sdf"] < np.float32(eps))
+
+
+def fp8_check(name, got, ref):
+    ferr = np.abs(got["fg"].astype(np.float64) - ref["sdf"])
+    gn = np.linalg.norm(ref["grad"], axis=1)
+    ok = gn > 1e-6 * np.median(gn)
+    ang = angle(got["grad"][ok].astype(np.float64), ref["grad"][ok])
+    record(name + "_fp8_check", sdf_max=float(ferr.max()), ang_p99=float(np.quantile(ang, 0.99)),
+           ang_max=float(ang.max()))
+    tol_f, tol_a = TOL["fp8"]
+    assert ferr.max() <= tol_f
+    assert np.quantile(ang, 0.99) <= 0.15 and ang.max() <= tol_a
+
+
+FP8_SHAPES = [((128,) * 4, 2), ((256,) * 8, 5), ((512,) * 3, 2), ((512,) * 8, 5)]
+
+
+@pytest.mark.parametrize("widths,skip", FP8_SHAPES)
+def test_fp8_shapes_geometric(widths, skip):
+    """E4M3 operands on geometric-init nets, 1 / 17 / 100 / 1000 points."""
+    spec = I.NetSpec(tuple(widths), skip=skip)
+    params = I.init_geometric(spec, 3)
+    for n in (1, 17, 100, 1000):
+        pts = I.uniform_points(n, 40 + n)
+        name = "fp8_%dx%d_s%d_n%d" % (widths[0], len(widths), skip, n)
+        got, ref = compare(name, spec, params, pts, "fp8", assert_gate=False)
+        fp8_check(name, got, ref)
+
+
+def test_wide_net_4m_points_sampled():
+    """3->512x8->1 skip 5, 4M uniform points in the benchmark's launch shape:
+    BF16, BF16x3 and FP8 on 4096 sampled outputs against FP64."""
+    spec, params, pts, eps = I.workload_inputs("wide4m")
+    idx = np.random.default_rng(4).choice(len(pts), 4096, replace=False)
+    ref = oracle.collide_project(spec, params, pts[idx], eps)
+    for precision in ("bf16", "bf16x3", "fp8"):
+        got = run_gpu(spec, params, pts, precision, eps)
+        sub = {k: v[idx] for k, v in got.items()}
+        ferr = np.abs(sub["fg"] - ref["sdf"])
+        ang = angle(sub["grad"].astype(np.float64), ref["grad"])
+        record("wide4m_sampled", precision=precision, sdf_max=float(ferr.max()),
+               ang_max=float(ang.max()), ang_p99=float(np.quantile(ang, 0.99)))
+        assert np.array_equal(got["hit"].astype(bool), got["sdf"] < np.float32(eps))
+        if precision == "bf16x3":
+            assert ferr.max() <= TOL["bf16x3"][0] and ang.max() <= TOL["bf16x3"][1]
+        if precision == "fp8":
+            fp8_check("wide4m", sub, ref)
 
 
 # ------------------------------------------------------------- exact cases

@@ -115,6 +115,24 @@ int sdf_query_grad(const sdf_net* net, const float* pts, int64_t n, float* sdf, 
 int collide_project(const sdf_net* net, float* pts, int64_t n, float eps, float* sdf,
                     float* normal, uint8_t* hit, void* stream);
 
+/* ---- a collider in its own frame (Sec. 4.2: moving a neural implicit surface) ----
+ *
+ * T: HOST pointer to a 4x4 row-major matrix [A t; 0 0 0 1] placing the network's
+ * frame in the world (rotation and translation; any invertible A is accepted).
+ * The network is evaluated at p' = A^{-1} (p - t); the gradient returned and
+ * used for the normal is the gradient of p -> f(A^{-1}(p - t)), i.e.
+ * A^{-T} grad f(p'), which for a rotation A is A grad f(p') as in Sec. 4.2; the
+ * vertex moves in the world frame, p + (eps - f(p')) N.  The matrix is read
+ * during the call (no retention).  Errors as the calls above, plus SDF_EINVAL
+ * for a NULL, non-finite or singular T or a last row other than (0, 0, 0, 1).
+ * Distances are only preserved by rigid T; a scaled A gives f(A^{-1}(p - t)). */
+int sdf_query_rigid(const sdf_net* net, const float* T, const float* pts, int64_t n, float* sdf,
+                    void* stream);
+int sdf_query_grad_rigid(const sdf_net* net, const float* T, const float* pts, int64_t n, float* sdf,
+                         float* grad, void* stream);
+int collide_project_rigid(const sdf_net* net, const float* T, float* pts, int64_t n, float eps,
+                          float* sdf, float* normal, uint8_t* hit, void* stream);
+
 /* ---- several colliders per call (one network per rigid object, Sec. 3.1) ---- */
 
 typedef struct sdf_group sdf_group; /* opaque; device tables of a fixed set of calls */

@@ -127,6 +127,21 @@ def collide_project(spec, params, pts, eps: float):
     return {"sdf": f, "grad": g, "normal": nrm, "hit": hit, "pts": out}
 
 
+def collide_project_rigid(spec, params, pts, eps: float, T):
+    """The path for a collider placed in the world by T = [A t; 0 1] (Sec. 4.2):
+    the network is evaluated at p' = A^{-1}(p - t), the gradient of
+    p -> f(A^{-1}(p - t)) is A^{-T} grad f(p') (for a rotation A: A grad f(p'),
+    the rotated normal of Sec. 4.2), and the vertex moves in the world frame."""
+    T = _d(T).reshape(4, 4)
+    A, t = T[:3, :3], T[:3, 3]
+    X = _d(pts).reshape(-1, 3)
+    local = np.linalg.solve(A, (X - t).T).T
+    f, gl = mlp_eval(spec, params, local)
+    g = np.linalg.solve(A.T, gl.T).T
+    out, nrm, hit = collide(X, f, g, eps)
+    return {"sdf": f, "grad": g, "normal": nrm, "hit": hit, "pts": out}
+
+
 def point_triangle(p, a, b, c):
     """(closest point, squared distance, Voronoi region id) for one triangle."""
     q, d2 = np.empty(3), np.empty(1)

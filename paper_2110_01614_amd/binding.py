@@ -56,6 +56,13 @@ def _load():
     lib.collide_project.argtypes = [vp, vp, i64, f32, vp, vp, vp, vp]
     lib.sdf_last_error.restype = ctypes.c_char_p
     lib.sdf_last_error.argtypes = []
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.sdf_query_rigid.restype = ctypes.c_int
+    lib.sdf_query_rigid.argtypes = [vp, fp, vp, i64, vp, vp]
+    lib.sdf_query_grad_rigid.restype = ctypes.c_int
+    lib.sdf_query_grad_rigid.argtypes = [vp, fp, vp, i64, vp, vp, vp]
+    lib.collide_project_rigid.restype = ctypes.c_int
+    lib.collide_project_rigid.argtypes = [vp, fp, vp, i64, f32, vp, vp, vp, vp]
     lib.sdf_group_create.restype = ctypes.c_int
     lib.sdf_group_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp),
                                      ctypes.POINTER(i64), f32, ctypes.POINTER(vp)]
@@ -165,23 +172,30 @@ class SdfNet:
             raise ValueError("pts must be a contiguous float32 CUDA tensor of shape [n, 3]")
         return pts
 
-    def query(self, pts, out=None):
+    def query(self, pts, out=None, T=None):
+        """f at every point; T (4x4, optional): the network's frame in the world."""
         import torch
         pts = self._pts(pts)
         out = torch.empty(pts.shape[0], device=pts.device, dtype=torch.float32) if out is None else out
-        sdf_query(self.handle, pts, pts.shape[0], out)
+        if T is None:
+            sdf_query(self.handle, pts, pts.shape[0], out)
+        else:
+            sdf_query_rigid(self.handle, T, pts, pts.shape[0], out)
         return out
 
-    def query_grad(self, pts, sdf=None, grad=None):
+    def query_grad(self, pts, sdf=None, grad=None, T=None):
         import torch
         pts = self._pts(pts)
         n = pts.shape[0]
         sdf = torch.empty(n, device=pts.device, dtype=torch.float32) if sdf is None else sdf
         grad = torch.empty(n, 3, device=pts.device, dtype=torch.float32) if grad is None else grad
-        sdf_query_grad(self.handle, pts, n, sdf, grad)
+        if T is None:
+            sdf_query_grad(self.handle, pts, n, sdf, grad)
+        else:
+            sdf_query_grad_rigid(self.handle, T, pts, n, sdf, grad)
         return sdf, grad
 
-    def collide_project(self, pts, eps, want=("sdf", "normal", "hit")):
+    def collide_project(self, pts, eps, want=("sdf", "normal", "hit"), T=None):
         """In place on pts; returns the requested optional outputs."""
         import torch
         pts = self._pts(pts)
@@ -193,8 +207,35 @@ class SdfNet:
             outs["normal"] = torch.empty(n, 3, device=pts.device, dtype=torch.float32)
         if "hit" in want:
             outs["hit"] = torch.empty(n, device=pts.device, dtype=torch.uint8)
-        collide_project(self.handle, pts, n, eps, outs.get("sdf"), outs.get("normal"), outs.get("hit"))
+        if T is None:
+            collide_project(self.handle, pts, n, eps, outs.get("sdf"), outs.get("normal"), outs.get("hit"))
+        else:
+            collide_project_rigid(self.handle, T, pts, n, eps, outs.get("sdf"), outs.get("normal"),
+                                  outs.get("hit"))
         return outs
+
+
+def _frame(T):
+    import numpy as np
+    t = np.ascontiguousarray(T, dtype=np.float32).reshape(16)
+    return t, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def sdf_query_rigid(handle, T, pts, n, sdf, stream=None):
+    t, tp = _frame(T)
+    return _check(lib.sdf_query_rigid(handle, tp, _ptr(pts), int(n), _ptr(sdf), _stream(stream)))
+
+
+def sdf_query_grad_rigid(handle, T, pts, n, sdf, grad, stream=None):
+    t, tp = _frame(T)
+    return _check(lib.sdf_query_grad_rigid(handle, tp, _ptr(pts), int(n), _ptr(sdf), _ptr(grad),
+                                           _stream(stream)))
+
+
+def collide_project_rigid(handle, T, pts, n, eps, sdf=None, normal=None, hit=None, stream=None):
+    t, tp = _frame(T)
+    return _check(lib.collide_project_rigid(handle, tp, _ptr(pts), int(n), float(eps), _ptr(sdf),
+                                            _ptr(normal), _ptr(hit), _stream(stream)))
 
 
 # ------------------------------------------------------------------ fitting

@@ -466,9 +466,34 @@ bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
 // Shared checks and launch for the three query entry points.
 template <int MODE>
 int run(const sdf_net* net, const float* pts_in, float* pts_out, int64_t n, float eps, float* sdf,
-        float* grad, float* normal, uint8_t* hit, void* stream) {
+        float* grad, float* normal, uint8_t* hit, void* stream, const float* T = nullptr) {
   g_err.clear();
   if (!net) return fail(SDF_EINVAL, "net is NULL");
+  KArgs a{};
+  if (T) {  // collider frame T = [A t; 0 1] (host, row-major)
+    for (int i = 0; i < 16; ++i)
+      if (!std::isfinite(T[i])) return fail(SDF_EINVAL, "T must be finite");
+    if (std::fabs(T[12]) > 1e-6f || std::fabs(T[13]) > 1e-6f || std::fabs(T[14]) > 1e-6f ||
+        std::fabs(T[15] - 1.0f) > 1e-6f)
+      return fail(SDF_EINVAL, "the last row of T must be (0, 0, 0, 1)");
+    const double m[3][3] = {{T[0], T[1], T[2]}, {T[4], T[5], T[6]}, {T[8], T[9], T[10]}};
+    const double det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+                       m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                       m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+    double scale = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) scale = std::max(scale, std::fabs(m[i][j]));
+    if (!(std::fabs(det) > 1e-9 * scale * scale * scale)) return fail(SDF_EINVAL, "T is singular");
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {  // adjugate / det
+        const int r0 = (j + 1) % 3, r1 = (j + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+        a.Ai[3 * i + j] = (float)((m[r0][c0] * m[r1][c1] - m[r0][c1] * m[r1][c0]) / det);
+      }
+    a.tr[0] = T[3];
+    a.tr[1] = T[7];
+    a.tr[2] = T[11];
+    a.rigid = 1;
+  }
   if (n < 0) return fail(SDF_EINVAL, "n < 0");
   if (MODE == MODE_PROJECT && !std::isfinite(eps)) return fail(SDF_EINVAL, "eps must be finite");
   if (n == 0) return SDF_OK;  // pointers may be NULL for an empty batch
@@ -481,7 +506,6 @@ int run(const sdf_net* net, const float* pts_in, float* pts_out, int64_t n, floa
   if (n == 0) return SDF_OK;
   const int64_t tiles = (n + kPtsPerBlock - 1) / kPtsPerBlock;
   if (2 * tiles > 0x7fffffff) return fail(SDF_EINVAL, "n too large");
-  KArgs a{};
   a.pts_in = pts_in;
   a.pts_out = pts_out;
   a.n = n;
@@ -527,6 +551,24 @@ int sdf_query_grad(const sdf_net* net, const float* pts, int64_t n, float* sdf, 
 int collide_project(const sdf_net* net, float* pts, int64_t n, float eps, float* sdf,
                     float* normal, uint8_t* hit, void* stream) {
   return run<MODE_PROJECT>(net, pts, pts, n, eps, sdf, nullptr, normal, hit, stream);
+}
+
+int sdf_query_rigid(const sdf_net* net, const float* T, const float* pts, int64_t n, float* sdf,
+                    void* stream) {
+  if (!T) return fail(SDF_EINVAL, "T is NULL");
+  return run<MODE_QUERY>(net, pts, nullptr, n, 0.0f, sdf, nullptr, nullptr, nullptr, stream, T);
+}
+
+int sdf_query_grad_rigid(const sdf_net* net, const float* T, const float* pts, int64_t n, float* sdf,
+                         float* grad, void* stream) {
+  if (!T) return fail(SDF_EINVAL, "T is NULL");
+  return run<MODE_GRAD>(net, pts, nullptr, n, 0.0f, sdf, grad, nullptr, nullptr, stream, T);
+}
+
+int collide_project_rigid(const sdf_net* net, const float* T, float* pts, int64_t n, float eps,
+                          float* sdf, float* normal, uint8_t* hit, void* stream) {
+  if (!T) return fail(SDF_EINVAL, "T is NULL");
+  return run<MODE_PROJECT>(net, pts, pts, n, eps, sdf, nullptr, normal, hit, stream, T);
 }
 
 }  // extern "C"

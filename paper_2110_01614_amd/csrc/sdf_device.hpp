@@ -45,6 +45,11 @@ struct KArgs {
   // of the forward (fsc[l]) and reverse (rsc[l]) contraction of layer l
   float fsc[kLMax + 1];
   float rsc[kLMax + 1];
+  // collider frame T = [A t; 0 1] (Sec. 4.2): the network is evaluated at
+  // p' = A^{-1} (p - t) and its gradient returned as A^{-T} grad' (rigid = 0: identity)
+  int rigid;
+  float Ai[9];  // A^{-1}, row-major
+  float tr[3];  // t
   float* ws_E;           // [L][n][W]: dLoss/dz_l per point
   float* ws_H;           // [L+1][n][W+16]: h_l, then x, y, z, 1, zeros (h_0 slot: x, y, z, 1 only)
   float* ws_U;           // [n][16]: dLoss/df, zeros
@@ -176,13 +181,32 @@ __device__ __forceinline__ float sum_lane_groups(float v) {
   return v;
 }
 
+// World point -> the network's frame.
+__device__ __forceinline__ void to_local(const KArgs& a, float& x0, float& x1, float& x2) {
+  if (!a.rigid) return;
+  const float d0 = x0 - a.tr[0], d1 = x1 - a.tr[1], d2 = x2 - a.tr[2];
+  x0 = __builtin_fmaf(a.Ai[0], d0, __builtin_fmaf(a.Ai[1], d1, a.Ai[2] * d2));
+  x1 = __builtin_fmaf(a.Ai[3], d0, __builtin_fmaf(a.Ai[4], d1, a.Ai[5] * d2));
+  x2 = __builtin_fmaf(a.Ai[6], d0, __builtin_fmaf(a.Ai[7], d1, a.Ai[8] * d2));
+}
+
 // Final per-point outputs, shared by every kernel family.  Only lanes of group
 // 0 (lanes 0..15) store; the other groups hold the same reduced values.
+// x0..x2: the vertex as loaded (world frame).  g0..g2: gradient in the
+// network's frame.
 template <int MODE>
 __device__ __forceinline__ void store_outputs(const KArgs& a, int64_t p, bool store, float f,
                                               float g0, float g1, float g2, float x0, float x1,
                                               float x2) {
   if (!store) return;
+  if (a.rigid) {  // grad_p f(A^{-1}(p - t)) = A^{-T} grad'
+    const float h0 = a.Ai[0] * g0 + a.Ai[3] * g1 + a.Ai[6] * g2;
+    const float h1 = a.Ai[1] * g0 + a.Ai[4] * g1 + a.Ai[7] * g2;
+    const float h2 = a.Ai[2] * g0 + a.Ai[5] * g1 + a.Ai[8] * g2;
+    g0 = h0;
+    g1 = h1;
+    g2 = h2;
+  }
   if constexpr (MODE == MODE_QUERY) {
     a.sdf[p] = f;
   } else if constexpr (MODE == MODE_GRAD) {

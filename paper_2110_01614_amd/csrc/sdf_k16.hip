@@ -129,9 +129,11 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     const int64_t p = base + tid;
     f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
     if (p < a.n) {
-      v[0] = a.pts_in[3 * p];
-      v[1] = a.pts_in[3 * p + 1];
-      v[2] = a.pts_in[3 * p + 2];
+      float x0 = a.pts_in[3 * p], x1 = a.pts_in[3 * p + 1], x2 = a.pts_in[3 * p + 2];
+      to_local(a, x0, x1, x2);
+      v[0] = x0;
+      v[1] = x1;
+      v[2] = x2;
     }
     xs[tid] = v;
   }
@@ -477,8 +479,13 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     f32x4 s = red[0][16 * wave + col];
 #pragma unroll
     for (int w = 1; w < NWV; ++w) s += red[w][16 * wave + col];
-    const f32x4 x = xs[16 * wave + col];
+    f32x4 x = xs[16 * wave + col];
     const int64_t p = base + 16 * wave + col;
+    if (a.rigid && p < a.n) {  // the vertex moves in the world frame
+      x[0] = a.pts_in[3 * p];
+      x[1] = a.pts_in[3 * p + 1];
+      x[2] = a.pts_in[3 * p + 2];
+    }
     store_outputs<MODE>(a, p, p < a.n && g == 0, s[0] + a.bo, s[1], s[2], s[3], x[0], x[1], x[2]);
   }
 }

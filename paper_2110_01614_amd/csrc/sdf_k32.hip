@@ -68,12 +68,14 @@ sdf_k32(const KArgs a) {
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int64_t p = (int64_t)tile * kPtsPerBlock + wave * kPtsPerWave + (lane & 15);
     const bool valid = p < a.n;
-    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;  // as loaded (world frame)
     if (valid) {
-      x0 = a.pts_in[3 * p];
-      x1 = a.pts_in[3 * p + 1];
-      x2 = a.pts_in[3 * p + 2];
+      w0 = a.pts_in[3 * p];
+      w1 = a.pts_in[3 * p + 1];
+      w2 = a.pts_in[3 * p + 2];
     }
+    float x0 = w0, x1 = w1, x2 = w2;  // in the network's frame
+    to_local(a, x0, x1, x2);
     __syncthreads();  // small weights visible; previous tile done with the ring
     for (int c = 0; c < kNBuf - 1; ++c)
       if (c < nch) issue_chunk<G>(a.stream, c, ring0, wave, lane);
@@ -270,7 +272,7 @@ sdf_k32(const KArgs a) {
         gx1 = sum_lane_groups(gx1);
         gx2 = sum_lane_groups(gx2);
       }
-      store_outputs<MODE>(a, p, valid && g == 0, f, gx0, gx1, gx2, x0, x1, x2);
+      store_outputs<MODE>(a, p, valid && g == 0, f, gx0, gx1, gx2, w0, w1, w2);
     }
   }
 }

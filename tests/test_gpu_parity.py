@@ -221,6 +221,64 @@ def test_wide_net_4m_points_sampled():
             fp8_check("wide4m", sub, ref)
 
 
+def rotation(seed):
+    q = np.random.default_rng(seed).normal(size=4)
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "bf16x3", "fp8"])
+def test_rigid_frame(precision):
+    """A collider moved by T = [R t; 0 1] (Sec. 4.2) against the FP64 oracle;
+    the identity frame reproduces the plain calls bit for bit."""
+    spec = I.NetSpec((256,) * 4, skip=2)
+    params = I.init_geometric(spec, 6)
+    T = np.eye(4)
+    T[:3, :3], T[:3, 3] = rotation(8), [0.25, -0.1, 0.05]
+    pts = (I.uniform_points(3000, 15) * 0.9 + T[:3, 3]).astype(np.float32)
+    eps = 0.005
+    ref = oracle.collide_project_rigid(spec, params, pts, eps, T)
+    net = B.SdfNet(spec, params, precision)
+    X = torch.from_numpy(pts).cuda()
+    fq = net.query(X, T=T)
+    fg, g = net.query_grad(X, T=T)
+    P = X.clone()
+    outs = net.collide_project(P, eps, T=T)
+    # identity frame == plain entry points
+    I4 = np.eye(4)
+    f_id, g_id = net.query_grad(X, T=I4)
+    f_pl, g_pl = net.query_grad(X)
+    torch.cuda.synchronize()
+    assert torch.equal(f_id, f_pl) and torch.equal(g_id, g_pl)
+    fq, fg, g = fq.cpu().numpy(), fg.cpu().numpy(), g.cpu().numpy().astype(np.float64)
+    P, hit = P.cpu().numpy(), outs["hit"].cpu().numpy()
+    assert np.array_equal(fq, fg) and np.array_equal(fg, outs["sdf"].cpu().numpy())
+    ferr = np.abs(fg - ref["sdf"])
+    ang = angle(g, ref["grad"])
+    record("rigid_frame", precision=precision, sdf_max=float(ferr.max()), ang_max=float(ang.max()),
+           ang_p99=float(np.quantile(ang, 0.99)))
+    assert np.array_equal(hit.astype(bool), fg < np.float32(eps))
+    miss = hit == 0
+    assert np.array_equal(P[miss].view(np.uint32), pts[miss].view(np.uint32))
+    tol_f, tol_a = TOL[precision]
+    if precision == "fp32":
+        assert np.all(ferr <= tol_f * (1 + np.abs(ref["sdf"]))) and ang.max() <= tol_a
+    elif precision == "bf16x3":
+        assert ferr.max() <= tol_f and ang.max() <= tol_a
+    elif precision == "fp8":
+        fp8_check("rigid", {"fg": fg, "grad": g}, ref)
+    if precision in ("fp32", "bf16x3"):  # moved vertices in the world frame
+        both = (hit == 1) & (ref["hit"] == 1)
+        dp = np.linalg.norm(P[both] - ref["pts"][both], axis=1)
+        assert np.all(dp <= tol_f * (1 + np.abs(ref["sdf"][both])) + np.abs(eps - ref["sdf"][both]) * tol_a
+                      + 1e-6)
+    with pytest.raises(B.SdfError):
+        net.query(X, T=np.zeros((4, 4)))  # singular, bad last row
+    net.close()
+
+
 # ------------------------------------------------------------- exact cases
 
 def plane_net(n, d, C=2.5, widths=(64,) * 6, skip=4, seed=5):

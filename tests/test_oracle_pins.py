@@ -137,6 +137,53 @@ def test_plane_embedded_in_mlp_is_exact():
     assert np.max(np.abs(g - n)) < 1e-15
 
 
+def rotation(seed):
+    """A proper rotation from a seeded unit quaternion."""
+    q = np.random.default_rng(seed).normal(size=4)
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def test_rigid_frame_moves_the_plane_in_closed_form():
+    """Sec. 4.2: a collider moved by T = [R t; 0 1] is the plane n.x = d moved by
+    T: f(p) = (R n).(p - t) - d, normal R n, and every hit lands on f = eps."""
+    n = np.array([0.6, -0.48, 0.64])
+    d, eps = 0.25, 0.01
+    spec, P = plane_net(n, d)
+    R, t = rotation(3), np.array([0.3, -0.2, 0.15])
+    T = np.eye(4)
+    T[:3, :3], T[:3, 3] = R, t
+    x = I.uniform_points(800, 13).astype(np.float64)
+    res = oracle.collide_project_rigid(spec, P, x, eps, T)
+    Rn = R @ n
+    assert np.max(np.abs(res["sdf"] - ((x - t) @ Rn - d))) < 1e-13
+    assert np.max(np.abs(res["normal"] - Rn)) < 1e-13
+    hit = res["hit"] == 1
+    assert hit.any() and (~hit).any()
+    assert np.max(np.abs((res["pts"][hit] - t) @ Rn - d - eps)) < 1e-13
+    assert np.array_equal(res["pts"][~hit], x[~hit])
+
+
+def test_rigid_frame_gradient_matches_differences_for_a_general_affine_map():
+    """The gradient of p -> f(A^{-1}(p - t)) against central differences, with a
+    non-orthogonal A (the transformation rule itself, not only rotations)."""
+    spec, P = random_net(21, (16, 16, 16), 0)
+    A = np.array([[1.2, 0.3, -0.1], [0.0, 0.9, 0.4], [0.2, -0.3, 1.1]])
+    T = np.eye(4)
+    T[:3, :3], T[:3, 3] = A, [0.1, 0.2, -0.3]
+    x = I.uniform_points(50, 14).astype(np.float64)
+    res = oracle.collide_project_rigid(spec, P, x, 0.0, T)
+    h = 1e-6
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = h
+        fp = oracle.collide_project_rigid(spec, P, x + e, 0.0, T)["sdf"]
+        fm = oracle.collide_project_rigid(spec, P, x - e, 0.0, T)["sdf"]
+        assert np.max(np.abs((fp - fm) / (2 * h) - res["grad"][:, c])) < 1e-6
+
+
 # ---------------------------------------------------------- collision step
 
 def test_projection_onto_analytic_sphere_is_closed_form():

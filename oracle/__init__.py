@@ -86,6 +86,13 @@ def _net(spec):
 
 
 def param_count(spec) -> int:
+    if getattr(spec, "fourier", 0):
+        from . import fourier
+        prev, n = 2 * spec.fourier, 3 * spec.fourier
+        for w in spec.widths:
+            n += w * prev + w
+            prev = w
+        return n + prev + 1
     L, w, skip, _ = _net(spec)
     return int(_load().orc_param_count(L, _p(w, _i32p), skip))
 
@@ -95,6 +102,9 @@ def mlp_eval(spec, params, pts, grad: bool = True, mode: str = "reverse"):
 
     mode "reverse" back-propagates (Sec. 3.2); "forward" propagates tangents.
     """
+    if getattr(spec, "fourier", 0):  # Fourier-feature input (numpy, oracle/fourier.py)
+        from . import fourier
+        return fourier.mlp_eval(spec, params, pts, grad)
     L, w, skip, beta = _net(spec)
     P, X = _d(params), _d(pts).reshape(-1, 3)
     if P.size != param_count(spec):

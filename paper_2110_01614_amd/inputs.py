@@ -35,6 +35,7 @@ class NetSpec:
     widths: tuple
     skip: int = 0          # 1-based hidden layer fed [h_{l-1}; x]; 0 = none
     beta: float = 100.0    # softplus sharpness
+    fourier: int = 0       # m > 0: input gamma(x) = [sin 2 pi B x, cos 2 pi B x], B [m][3]
 
     @property
     def depth(self) -> int:
@@ -45,8 +46,10 @@ def layer_shapes(spec: NetSpec):
     """(out, in) of every affine map, hidden layers first, output layer last."""
     if spec.skip == 1 or spec.skip < 0 or spec.skip > spec.depth:
         raise ValueError("skip must be 0 or in [2, depth]")
+    if spec.fourier and spec.skip:
+        raise ValueError("a Fourier-feature net has no skip input")
     shapes = []
-    prev = 3
+    prev = 2 * spec.fourier if spec.fourier else 3
     for l, w in enumerate(spec.widths, start=1):
         k = prev + (3 if l == spec.skip else 0)
         shapes.append((int(w), int(k)))
@@ -56,7 +59,19 @@ def layer_shapes(spec: NetSpec):
 
 
 def param_count(spec: NetSpec) -> int:
-    return sum(o * i + o for o, i in layer_shapes(spec))
+    """Flat parameters: [B (m x 3, Fourier nets only)], then W_l, b_l, ..., w_o, b_o."""
+    return 3 * spec.fourier + sum(o * i + o for o, i in layer_shapes(spec))
+
+
+def init_fourier(spec: NetSpec, seed: int, sigma: float = 2.0) -> np.ndarray:
+    """Fourier-feature net (Sec. 3.1, Fourier features): B ~ N(0, sigma^2) [m][3],
+    hidden W ~ N(0, 1/K), biases N(0, 0.01^2), output w_o ~ N(0, 1/W)."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0.0, sigma, size=3 * spec.fourier)]
+    for o, i in layer_shapes(spec):
+        parts.append(rng.normal(0.0, 1.0 / math.sqrt(i), size=o * i))
+        parts.append(rng.normal(0.0, 0.01, size=o))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def _pack(mats):

@@ -184,6 +184,52 @@ def test_rigid_frame_gradient_matches_differences_for_a_general_affine_map():
         assert np.max(np.abs((fp - fm) / (2 * h) - res["grad"][:, c])) < 1e-6
 
 
+def torch_fourier_mlp(spec, params, pts):
+    """Fourier-feature net with torch float64 autograd, from the flat layout."""
+    P = torch.tensor(np.asarray(params, dtype=np.float64))
+    x = torch.tensor(np.asarray(pts, dtype=np.float64), requires_grad=True)
+    m = spec.fourier
+    B = P[:3 * m].view(m, 3)
+    off = 3 * m
+    proj = 2 * math.pi * x @ B.T
+    h = torch.cat([torch.sin(proj), torch.cos(proj)], dim=1)
+    for o, i in I.layer_shapes(spec)[:-1]:
+        W = P[off:off + o * i].view(o, i)
+        off += o * i
+        b = P[off:off + o]
+        off += o
+        h = torch.nn.functional.softplus(h @ W.T + b, beta=spec.beta, threshold=30.0)
+    _, i = I.layer_shapes(spec)[-1]
+    f = h @ P[off:off + i] + P[off + i]
+    (g,) = torch.autograd.grad(f.sum(), x)
+    return f.detach().numpy(), g.numpy()
+
+
+@pytest.mark.parametrize("widths,m,sigma", [((32, 32), 16, 1.0), ((64,) * 4, 32, 3.0), ((24, 40, 16), 5, 2.0)])
+def test_fourier_features_match_torch_autograd(widths, m, sigma):
+    """Sec. 3.1 / 4.3 Fourier-feature input: f and grad f against torch autograd."""
+    spec = I.NetSpec(tuple(widths), fourier=m)
+    P = I.init_fourier(spec, 9, sigma)
+    x = I.uniform_points(300, 16).astype(np.float64)
+    f, g = oracle.mlp_eval(spec, P, x)
+    ft, gt = torch_fourier_mlp(spec, P, x)
+    assert np.max(np.abs(f - ft)) < 1e-12 * (1 + np.abs(ft).max())
+    assert np.max(np.abs(g - gt)) < 1e-11 * (1 + np.abs(gt).max())
+
+
+def test_fourier_gradient_matches_central_differences():
+    spec = I.NetSpec((32, 32, 32), fourier=16)
+    P = I.init_fourier(spec, 10, 2.0)
+    x = I.uniform_points(40, 17).astype(np.float64)
+    _, g = oracle.mlp_eval(spec, P, x)
+    h = 1e-6
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = h
+        fd = (oracle.mlp_eval(spec, P, x + e, grad=False) - oracle.mlp_eval(spec, P, x - e, grad=False)) / (2 * h)
+        assert np.max(np.abs(fd - g[:, c])) < 1e-6 * (1 + np.abs(g).max())
+
+
 # ---------------------------------------------------------- collision step
 
 def test_projection_onto_analytic_sphere_is_closed_form():

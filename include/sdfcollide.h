@@ -66,6 +66,10 @@ enum { SDF_FP32 = 0, SDF_BF16 = 1, SDF_FP16 = 2, SDF_BF16X3 = 3, SDF_FP8 = 4 };
  * Hidden layer l (1-based) has width[l-1] units and softplus activation
  * softplus_beta(z) = log(1 + exp(beta z)) / beta.  If skip_layer = s > 0,
  * hidden layer s takes [h_{s-1}; x] (hidden features first, then x, y, z).
+ * Fourier features: with fourier = m > 0 the network's input is
+ * gamma(x) = [sin(2 pi B x), cos(2 pi B x)] (B an m x 3 matrix, fixed), layer 1
+ * has K = 2m inputs and there is no skip input (skip_layer must be 0); this
+ * build requires 2m == width and BF16, FP16 or BF16X3 operands.
  * This build has kernels for equal hidden widths of 64, 128, 256 or 512 (512:
  * 16-bit and FP8 precisions only; FP8: 128 and up), depth 2..8, skip 0 or
  * 2..depth; other shapes return SDF_EUNSUPPORTED. */
@@ -75,14 +79,16 @@ typedef struct {
   int32_t skip_layer;
   float beta;
   int32_t precision;
+  int32_t fourier; /* m > 0: Fourier-feature input (Sec. 3.1, Sec. 4.3), see below */
 } sdf_net_desc;
 
 typedef struct sdf_net sdf_net; /* opaque; owns device copies of packed weights */
 
 /* Number of float32 parameters of `desc` in the flat layout below, or -1 if
  * the description is malformed.  Flat layout (the concatenation of every
- * nn.Linear weight then bias): for l = 1..L, W_l row-major [width_l][K_l] then
- * b_l[width_l], K_1 = 3, K_l = width_{l-1} (+3 at the skip layer); then
+ * nn.Linear weight then bias): for a Fourier net first B row-major [m][3];
+ * then for l = 1..L, W_l row-major [width_l][K_l] then b_l[width_l], K_1 = 3
+ * (2m with Fourier input), K_l = width_{l-1} (+3 at the skip layer); then
  * w_o[width_L], b_o. */
 int64_t sdf_param_count(const sdf_net_desc* desc);
 

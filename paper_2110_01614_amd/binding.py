@@ -25,7 +25,8 @@ class sdf_net_desc(ctypes.Structure):
                 ("width", ctypes.c_int32 * SDF_MAX_HIDDEN),
                 ("skip_layer", ctypes.c_int32),
                 ("beta", ctypes.c_float),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32),
+                ("fourier", ctypes.c_int32)]
 
 
 class SdfError(RuntimeError):
@@ -90,7 +91,7 @@ def _check(rc):
     return rc
 
 
-def make_desc(widths, skip=0, beta=100.0, precision="fp32") -> sdf_net_desc:
+def make_desc(widths, skip=0, beta=100.0, precision="fp32", fourier=0) -> sdf_net_desc:
     d = sdf_net_desc()
     d.n_hidden = len(widths)
     for i, w in enumerate(widths):
@@ -98,6 +99,7 @@ def make_desc(widths, skip=0, beta=100.0, precision="fp32") -> sdf_net_desc:
     d.skip_layer = int(skip)
     d.beta = float(beta)
     d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    d.fourier = int(fourier)
     return d
 
 
@@ -150,7 +152,7 @@ class SdfNet:
         self.spec = spec
         self.precision = precision
         self.device = device
-        self.desc = make_desc(spec.widths, spec.skip, spec.beta, precision)
+        self.desc = make_desc(spec.widths, spec.skip, spec.beta, precision, getattr(spec, "fourier", 0))
         self.handle = sdf_net_create(self.desc, params, device)
 
     def close(self):

@@ -67,6 +67,8 @@ int check_desc(const sdf_net_desc* d, int* W, int* L, int* skip) {
   if (d->skip_layer == 1 || d->skip_layer < 0 || d->skip_layer > d->n_hidden)
     return fail(SDF_EINVAL, "skip_layer must be 0 or in [2, n_hidden]");
   if (!std::isfinite(d->beta) || d->beta <= 0.0f) return fail(SDF_EINVAL, "beta must be finite and > 0");
+  if (d->fourier < 0 || d->fourier > 4096) return fail(SDF_EINVAL, "fourier must be in [0, 4096]");
+  if (d->fourier > 0 && d->skip_layer != 0) return fail(SDF_EINVAL, "a Fourier-feature net has no skip input");
   if (d->precision != SDF_FP32 && d->precision != SDF_BF16 && d->precision != SDF_FP16 &&
       d->precision != SDF_BF16X3 && d->precision != SDF_FP8)
     return fail(SDF_EINVAL, "unknown precision");
@@ -85,13 +87,15 @@ int check_supported(int W, const sdf_net_desc* d) {
     return fail(SDF_EUNSUPPORTED, "width 512 has 16-bit and FP8 kernels only");
   if (W < 128 && d->precision == SDF_FP8)
     return fail(SDF_EUNSUPPORTED, "FP8 needs width 128, 256 or 512 (K-blocks of 128)");
+  if (d->fourier > 0 && (2 * d->fourier != W || d->precision == SDF_FP32 || d->precision == SDF_FP8))
+    return fail(SDF_EUNSUPPORTED, "Fourier features need 2m == width and BF16, FP16 or BF16X3 operands");
   if (d->n_hidden < 2 || d->n_hidden > kLMax) return fail(SDF_EUNSUPPORTED, "depth must be in [2, 8]");
   return SDF_OK;
 }
 
 int64_t count_params(const sdf_net_desc* d) {
-  int64_t c = 0;
-  int prev = 3;
+  int64_t c = 3 * (int64_t)d->fourier;  // B of the Fourier mapping
+  int prev = d->fourier ? 2 * d->fourier : 3;
   for (int l = 1; l <= d->n_hidden; ++l) {
     const int w = d->width[l - 1];
     const int k = prev + (l == d->skip_layer ? 3 : 0);
@@ -103,16 +107,17 @@ int64_t count_params(const sdf_net_desc* d) {
 
 // Host view of the flat parameters.
 struct Net {
-  int W, L, skip;
+  int W, L, skip, m;  // m: Fourier frequencies (0: the input is x itself)
   std::vector<const float*> Wl, bl;  // index l = 1..L
   const float* wo;
   float bo;
-  int K(int l) const { return (l == 1 ? 3 : W) + (l == skip ? 3 : 0); }
+  const float* B;  // [m][3]
+  int K(int l) const { return (l == 1 ? (m ? 2 * m : 3) : W) + (l == skip ? 3 : 0); }
 };
 
-Net view(const float* P, int W, int L, int skip) {
-  Net n{W, L, skip, std::vector<const float*>(L + 1), std::vector<const float*>(L + 1), nullptr, 0.0f};
-  const float* q = P;
+Net view(const float* P, int W, int L, int skip, int m) {
+  Net n{W, L, skip, m, std::vector<const float*>(L + 1), std::vector<const float*>(L + 1), nullptr, 0.0f, P};
+  const float* q = P + 3 * (size_t)m;
   for (int l = 1; l <= L; ++l) {
     n.Wl[l] = q;
     q += (size_t)W * n.K(l);
@@ -228,7 +233,8 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
   if (device < 0 || device >= ndev) return fail(SDF_EINVAL, "no such device");
 
-  const Net n = view(params, W, L, skip);
+  const int m = desc->fourier;
+  const Net n = view(params, W, L, skip, m);
   const int prec = desc->precision;
   const double kappa = (double)desc->beta / std::log(2.0);  // beta * log2(e)
   std::vector<int> S = (prec == SDF_FP32) ? std::vector<int>(L + 1, 0) : reverse_scales(n);
@@ -252,12 +258,19 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
   const SmallLayout SL{W};
   std::vector<float> sm(SL.floats(), 0.0f);
   for (int j = 0; j < W; ++j) {
-    const float* w1 = n.Wl[1] + (size_t)j * n.K(1);
-    for (int c = 0; c < 3; ++c) {
-      sm[SL.l1() + 4 * j + c] = (float)(kappa * w1[c]);
-      sm[SL.l1g() + 4 * j + c] = (float)std::ldexp((double)w1[c], -S[1]);
+    if (m) {  // Fourier input: feature j = sin(2 pi (b . x + phase)), phase 1/4 for the cosines
+      const float* b = n.B + 3 * (size_t)(j % m);
+      for (int c = 0; c < 3; ++c) sm[SL.l1() + 4 * j + c] = b[c];
+      sm[SL.l1() + 4 * j + 3] = j < m ? 0.0f : 0.25f;
+      sm[SL.l1g() + j] = (float)(kappa * n.bl[1][j]);  // layer-1 bias of the MFMA layer
+    } else {
+      const float* w1 = n.Wl[1] + (size_t)j * n.K(1);
+      for (int c = 0; c < 3; ++c) {
+        sm[SL.l1() + 4 * j + c] = (float)(kappa * w1[c]);
+        sm[SL.l1g() + 4 * j + c] = (float)std::ldexp((double)w1[c], -S[1]);
+      }
+      sm[SL.l1() + 4 * j + 3] = (float)(kappa * n.bl[1][j]);
     }
-    sm[SL.l1() + 4 * j + 3] = (float)(kappa * n.bl[1][j]);
     if (skip) {
       const float* ws = n.Wl[skip] + (size_t)j * n.K(skip) + W;
       for (int c = 0; c < 3; ++c) {
@@ -336,13 +349,17 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
           }
         }
   };
+  // Contractions on MFMA: layers 2..L, and layer 1 too for Fourier input
+  // (K = 2m = W; its forward weights carry kappa since gamma is not rescaled).
+  const int nf = m ? 1 : 2;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int step = 0; step < L - 1; ++step) {
-      const int l = pass == 0 ? 2 + step : L - step;
+    for (int step = 0; step < L - nf + 1; ++step) {
+      const int l = pass == 0 ? nf + step : L - step;
       const float* Wl = n.Wl[l];
       const int K = n.K(l);
       const float sc = (float)std::ldexp(1.0, S[l - 1] - S[l]);
-      auto fwd = [&](int r, int c) { return Wl[(size_t)r * K + c]; };
+      const float fk = (l == 1) ? (float)kappa : 1.0f;
+      auto fwd = [&](int r, int c) { return Wl[(size_t)r * K + c] * fk; };
       auto rev = [&](int r, int c) { return Wl[(size_t)c * K + r] * sc; };
       if (prec == SDF_FP32) {
         if (pass == 0) emit32(fwd); else emit32(rev);
@@ -524,6 +541,7 @@ int run(const sdf_net* net, const float* pts_in, float* pts_out, int64_t n, floa
   }
   a.L = net->L;
   a.skip = net->skip;
+  a.ff = net->desc.fourier > 0 ? 1 : 0;
   a.nch = (net->L - 1) * net->chunks_per_layer * (MODE == MODE_QUERY ? 1 : 2);
   a.ntiles = (int)tiles;
   int prev = 0;
@@ -614,6 +632,7 @@ int train_check(const sdf_net_desc* desc, int* W, int* L, int* skip) {
   rc = check_supported(*W, desc);
   if (rc) return rc;
   if (desc->precision != SDF_FP32) return fail(SDF_EUNSUPPORTED, "fitting runs in FP32 (precision must be SDF_FP32)");
+  if (desc->fourier) return fail(SDF_EUNSUPPORTED, "fitting takes networks without Fourier input");
   return SDF_OK;
 }
 
@@ -808,6 +827,8 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
       a.small = net->d_small;
       a.L = net->L;
       a.skip = net->skip;
+      a.ff = net->desc.fourier > 0 ? 1 : 0;
+  a.ff = net->desc.fourier > 0 ? 1 : 0;
       for (int l = 0; l <= kLMax; ++l) {
         a.fsc[l] = net->fsc[l];
         a.rsc[l] = net->rsc[l];

@@ -36,6 +36,7 @@ struct KArgs {
   float* scratch;        // FP32 kernels: per-slot sigma stack
   int L;                 // hidden layers
   int skip;              // 0 or 2..L
+  int ff;                // 1: Fourier-feature input (layer 1 is an MFMA layer over gamma(x))
   int nch;               // chunks streamed per tile
   int ntiles;            // ceil(n / 64)
   // fitting (MODE_TRAIN) only: per-point targets and the per-chunk workspace

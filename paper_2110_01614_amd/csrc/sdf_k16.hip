@@ -121,8 +121,10 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   const int g = lane >> 4, col = lane & 15;
   const int L = a.L, skip = a.skip;
   const int64_t base = (int64_t)tile * PTS;
-  const unsigned char* fwd = a.stream;  // layers 2..L, LAYER_BYTES each
-  const unsigned char* rev = a.stream + (size_t)(L - 1) * G::LAYER_BYTES;  // layers L..2
+  // first layer on MFMA: 2, or 1 with Fourier input (its K = 2m = W inputs are gamma(x))
+  const int nf = a.ff ? 1 : 2;
+  const unsigned char* fwd = a.stream;  // layers nf..L, LAYER_BYTES each
+  const unsigned char* rev = a.stream + (size_t)(L - nf + 1) * G::LAYER_BYTES;  // layers L..nf
 
   // ---- points (to LDS), small weights ----
   if (tid < PTS) {
@@ -237,23 +239,46 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     }
   };
 
-  // ---- layer 1: y = kappa (W1 x + b1) ----
+  // b_j . x + phase_j of Fourier feature j, reduced to [-1/2, 1/2] revolutions
+  auto ff_arg = [&](const f32x4& b, const f32x4& x) {
+    const float v = __builtin_fmaf(b.x, x[0], __builtin_fmaf(b.y, x[1], __builtin_fmaf(b.z, x[2], b.w)));
+    return v - __builtin_rintf(v);
+  };
+  if (!a.ff) {
+    // ---- layer 1: y = kappa (W1 x + b1) ----
 #pragma unroll
-  for (int mt = 0; mt < MTW; ++mt) {
-    f32x4 w4[4];
+    for (int mt = 0; mt < MTW; ++mt) {
+      f32x4 w4[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) w4[i] = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * feat(mt, i)]);
+      for (int i = 0; i < 4; ++i) w4[i] = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * feat(mt, i)]);
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) {
-      const f32x4 x = xs[16 * ct + col];
-      f32x4 r;
+      for (int ct = 0; ct < NCT; ++ct) {
+        const f32x4 x = xs[16 * ct + col];
+        f32x4 r;
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        r[i] = softplus2(__builtin_fmaf(w4[i].x, x[0], __builtin_fmaf(w4[i].y, x[1], __builtin_fmaf(w4[i].z, x[2], w4[i].w))));
-      put(&act[0][0][0], mt, ct, r, 1);
+        for (int i = 0; i < 4; ++i)
+          r[i] = softplus2(__builtin_fmaf(w4[i].x, x[0], __builtin_fmaf(w4[i].y, x[1], __builtin_fmaf(w4[i].z, x[2], w4[i].w))));
+        put(&act[0][0][0], mt, ct, r, 1);
+      }
+    }
+    keep_own(1);
+  } else {
+    // ---- Fourier input: gamma_j(x) = sin(2 pi (b_j . x + phase_j)), phase 1/4 for the cosines ----
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) {
+      f32x4 b4[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b4[i] = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * feat(mt, i)]);
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const f32x4 x = xs[16 * ct + col];
+        f32x4 gm;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) gm[i] = __builtin_amdgcn_sinf(ff_arg(b4[i], x));  // sin(2 pi v)
+        put(&act[1][0][0], mt, ct, gm, 0);
+      }
     }
   }
-  keep_own(1);
 
   // One hidden layer's contraction for this wave: acc[mt][ct] += A(mt, kb) B(kb, ct).
   // The K-blocks are taken in the order kb0, kb0 + 1, ... (mod KB).  When the
@@ -319,20 +344,22 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     }
   };
 
-  // ---- hidden layers 2..L, forward ----
+  // ---- hidden layers nf..L, forward ----
 #pragma unroll
-  for (int l = 2; l <= kLMax; ++l) {
+  for (int l = 1; l <= kLMax; ++l) {
     if (l > L) break;
+    if (l < nf) continue;
     const int t = l - 1;  // exchange step: read act[(t-1)&1], write act[t&1]
     const unsigned char* in = &act[(t - 1) & 1][0][0];
     unsigned char* out = &act[t & 1][0][0];
-    const unsigned char* layer = fwd + (size_t)(l - 2) * G::LAYER_BYTES;
+    const unsigned char* layer = fwd + (size_t)(l - nf) * G::LAYER_BYTES;
     const unsigned char* next =
         (l < L) ? layer + G::LAYER_BYTES : (MODE != MODE_QUERY ? rev : nullptr);
     f32x4 acc[MTW][NCT];
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
-      const f32x4 b = *reinterpret_cast<const f32x4*>(&sm[SL.bias(l) + 16 * (MTW * wave + mt) + 4 * g]);
+      const int boff = (l == 1) ? SL.l1g() : SL.bias(l);  // layer 1: Fourier input only
+      const f32x4 b = *reinterpret_cast<const f32x4*>(&sm[boff + 16 * (MTW * wave + mt) + 4 * g]);
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[mt][ct] = b;
     }
@@ -408,16 +435,16 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     }
   }
 
-  // ---- reverse sweep over W_l^T, l = L..2 ----
+  // ---- reverse sweep over W_l^T, l = L..nf ----
   if constexpr (MODE != MODE_QUERY) {
 #pragma unroll
-    for (int l = kLMax; l >= 2; --l) {
-      if (l > L) continue;
+    for (int l = kLMax; l >= 1; --l) {
+      if (l > L || l < nf) continue;
       const int t = 2 * L - l;
       const unsigned char* in = &act[(t - 1) & 1][0][0];
       unsigned char* out = &act[t & 1][0][0];
       const unsigned char* layer = rev + (size_t)(L - l) * G::LAYER_BYTES;
-      const unsigned char* next = (l > 2) ? layer + G::LAYER_BYTES : nullptr;
+      const unsigned char* next = (l > nf) ? layer + G::LAYER_BYTES : nullptr;
       f32x4 acc[MTW][NCT];
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt)
@@ -459,14 +486,42 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
                 part[ct][3] = __builtin_fmaf(wg[i].z, d[i], part[ct][3]);
               }
             }
-            if (l > 2) put(out, mt, ct, d, 0);
+            if (l > 2 || a.ff) put(out, mt, ct, d, 0);
           }
         }
         if constexpr (decltype(TOX)::value)
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) flush(ct, part[ct], true);
       };
-      if (l == 2 || l - 1 == skip)
+      // l == 1 (Fourier input): acc = d f / d gamma for this wave's features;
+      // grad x += sum_j acc_j 2 pi cos(2 pi (b_j . x + phase_j)) b_j
+      auto ff_epi = [&]() {
+        f32x4 part[NCT];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) part[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+          f32x4 b4[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) b4[i] = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * feat(mt, i)]);
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            const f32x4 x = xs[16 * ct + col];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float s = acc[mt][ct][i] * 6.28318530717958647f * __builtin_amdgcn_cosf(ff_arg(b4[i], x));
+              part[ct][1] = __builtin_fmaf(b4[i].x, s, part[ct][1]);
+              part[ct][2] = __builtin_fmaf(b4[i].y, s, part[ct][2]);
+              part[ct][3] = __builtin_fmaf(b4[i].z, s, part[ct][3]);
+            }
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) flush(ct, part[ct], true);
+      };
+      if (l == 1)
+        ff_epi();
+      else if ((l == 2 && !a.ff) || l - 1 == skip)
         bwd_epi(std::true_type{});
       else
         bwd_epi(std::false_type{});

@@ -77,6 +77,20 @@ def test_precision_width_combinations_without_kernels(widths, precision):
     assert e.value.code == B.SDF_EUNSUPPORTED
 
 
+def test_fourier_descriptions():
+    from paper_2110_01614_amd import inputs as I
+    spec = I.NetSpec((256,) * 4, fourier=128)
+    d = B.make_desc(spec.widths, 0, precision="bf16", fourier=128)
+    assert B.sdf_param_count(d) == I.param_count(spec)
+    d = B.make_desc((256,) * 4, 2, precision="bf16", fourier=128)  # no skip with Fourier input
+    assert B.sdf_param_count(d) == -1
+    for widths, m, prec in [((256,) * 4, 64, "bf16"), ((256,) * 4, 128, "fp32"), ((256,) * 4, 128, "fp8")]:
+        d = B.make_desc(widths, 0, precision=prec, fourier=m)
+        with pytest.raises(B.SdfError) as e:
+            B.sdf_net_create(d, np.zeros(B.sdf_param_count(d), np.float32))
+        assert e.value.code == B.SDF_EUNSUPPORTED
+
+
 def test_unknown_precision_is_rejected():
     d = B.make_desc((128,) * 3, 0)
     d.precision = 7

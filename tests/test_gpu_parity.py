@@ -279,6 +279,23 @@ def test_rigid_frame(precision):
     net.close()
 
 
+FF_SHAPES = [((128,) * 4, 64), ((256,) * 4, 128), ((256,) * 8, 128)]
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16", "bf16x3"])
+@pytest.mark.parametrize("widths,m", FF_SHAPES)
+def test_fourier_features(widths, m, precision):
+    """Fourier-feature input (Sec. 3.1, Sec. 4.3; the timed nets are 256 x 4 and
+    256 x 8): layer 1 runs on MFMA over gamma(x), and the reverse sweep continues
+    through the mapping.  1000 points (15 full tiles and a ragged one) and 17."""
+    spec = I.NetSpec(tuple(widths), fourier=m)
+    params = I.init_fourier(spec, 11, 2.0)
+    for n in (17, 1000):
+        pts = I.uniform_points(n, 21 + n)
+        compare("fourier_%dx%d_n%d" % (widths[0], len(widths), n), spec, params, pts, precision,
+                assert_gate=precision == "bf16x3")
+
+
 # ------------------------------------------------------------- exact cases
 
 def plane_net(n, d, C=2.5, widths=(64,) * 6, skip=4, seed=5):

@@ -156,12 +156,15 @@ def colliders(torch, B, I, steps, precision="bf16"):
             grp.collide_project()
     ms_graph = timed(graph.replay, max(1, steps // 10)) / 30
     del graph
+    per_net = grp.autotune()
+    ms_tuned = timed(grp.collide_project, steps)
     grp.close()
     for net in nets:
         net.close()
     return {"workload": "16 colliders, widths 128/256/512, depths 4-8, %d vertices, seed 5" % n,
             "precision": precision, "points": n,
             "grouped_ms": ms_group, "per_network_ms": ms_single, "graph_30_passes_ms_per_pass": ms_graph,
+            "autotuned_ms": ms_tuned, "autotuned_launch": "per network" if per_net else "per width class",
             "grouped_points_per_s": n / (ms_group * 1e-3), "grouped_tflops": flops / (ms_group * 1e-3) / 1e12}
 
 

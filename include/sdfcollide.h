@@ -161,6 +161,29 @@ int sdf_group_collide_project(const sdf_group* grp, void* stream);
 /* Frees the group's device tables (not the networks or buffers). */
 int sdf_group_destroy(sdf_group* grp);
 
+/* ---- autotuning of tile shapes and launch shape ----
+ *
+ * sdf_net_autotune times the tile variants of the network's collide_project
+ * kernel (BF16 and FP16 at widths 128-512: variant 0 = the default tile,
+ * variant 1 = half the points per workgroup with twice the weight prefetch)
+ * on n_sample points spread over [-1, 1]^3, in a scratch buffer it allocates
+ * and frees, and keeps the faster for later collide_project calls on this
+ * handle (other shapes and precisions: variant 0).  *variant (nullable)
+ * receives the choice.  Synchronous on `stream`; call it before the handle is
+ * shared across streams.  Every variant computes the same values per point.
+ *
+ * sdf_group_autotune times, on scratch copies of the members' vertices (the
+ * members are not moved), each width class's tile variants inside the
+ * grouped launch and then one launch per width class against one launch per
+ * network, and keeps the faster configuration for sdf_group_collide_project.
+ * *per_network (nullable) receives 1 when per-network launches were chosen.
+ * Allocates and frees its scratch; synchronous on `stream`. */
+int sdf_net_autotune(sdf_net* net, int64_t n_sample, void* stream, int* variant);
+/* Sets the tile variant directly (e.g. a cached autotune result): 0 always,
+ * 1 where sdf_net_autotune has a choice (else SDF_EUNSUPPORTED). */
+int sdf_net_set_tile_variant(sdf_net* net, int variant);
+int sdf_group_autotune(sdf_group* grp, void* stream, int* per_network);
+
 /* ---- fitting (Sec. 3.1): MLP regressed onto sampled signed distances ---- */
 
 /* Device workspace bytes sdf_train_step needs for a batch of n points with

@@ -69,6 +69,12 @@ def _load():
                                      ctypes.POINTER(i64), f32, ctypes.POINTER(vp)]
     lib.sdf_group_collide_project.restype = ctypes.c_int
     lib.sdf_group_collide_project.argtypes = [vp, vp]
+    lib.sdf_net_autotune.restype = ctypes.c_int
+    lib.sdf_net_autotune.argtypes = [vp, i64, vp, ctypes.POINTER(ctypes.c_int)]
+    lib.sdf_net_set_tile_variant.restype = ctypes.c_int
+    lib.sdf_net_set_tile_variant.argtypes = [vp, ctypes.c_int]
+    lib.sdf_group_autotune.restype = ctypes.c_int
+    lib.sdf_group_autotune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int)]
     lib.sdf_group_destroy.restype = ctypes.c_int
     lib.sdf_group_destroy.argtypes = [vp]
     lib.sdf_train_workspace_bytes.restype = i64
@@ -154,6 +160,13 @@ class SdfNet:
         self.device = device
         self.desc = make_desc(spec.widths, spec.skip, spec.beta, precision, getattr(spec, "fourier", 0))
         self.handle = sdf_net_create(self.desc, params, device)
+
+    def autotune(self, n_sample=1 << 18, stream=None) -> int:
+        """Time the collide_project tile variants and keep the faster; returns its index."""
+        return sdf_net_autotune(self.handle, n_sample, stream)
+
+    def set_tile_variant(self, variant: int):
+        _check(lib.sdf_net_set_tile_variant(self.handle, int(variant)))
 
     def close(self):
         if self.handle:
@@ -326,6 +339,18 @@ def sdf_group_destroy(group):
     return _check(lib.sdf_group_destroy(group))
 
 
+def sdf_net_autotune(handle, n_sample=1 << 18, stream=None) -> int:
+    v = ctypes.c_int(0)
+    _check(lib.sdf_net_autotune(handle, int(n_sample), _stream(stream), ctypes.byref(v)))
+    return v.value
+
+
+def sdf_group_autotune(group, stream=None) -> int:
+    v = ctypes.c_int(0)
+    _check(lib.sdf_group_autotune(group, _stream(stream), ctypes.byref(v)))
+    return v.value
+
+
 class SdfGroup:
     """A fixed set of (network, vertex tensor) pairs projected in one pass."""
 
@@ -338,6 +363,10 @@ class SdfGroup:
 
     def collide_project(self, stream=None):
         sdf_group_collide_project(self.handle, stream)
+
+    def autotune(self, stream=None) -> int:
+        """Pick tile variants and launch shape by timing; returns 1 for per-network launches."""
+        return sdf_group_autotune(self.handle, stream)
 
     def close(self):
         if self.handle:

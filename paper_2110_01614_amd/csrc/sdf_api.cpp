@@ -14,9 +14,9 @@
 #include "sdf_device.hpp"
 
 namespace sdfc {
-template <int W, int PREC, int MODE>
+template <int W, int PREC, int MODE, int VAR>
 __global__ void sdf_k16(const KArgs a);
-template <int W, int PREC, int MODE>
+template <int W, int PREC, int MODE, int VAR>
 __global__ void sdf_k16_group(const KArgs* nets, const int* tile_start, int n_nets, int tile0);
 template <int W, int MODE>
 __global__ void sdf_k32(const KArgs a);
@@ -40,6 +40,7 @@ struct sdf_net {
   float* d_small = nullptr;
   float* d_scratch = nullptr;  // FP32 sigma stack, one slot per resident workgroup
   int slots = 0;
+  int variant = 0;            // tile variant of the 16-bit collide_project kernel (autotuner)
   float fsc[kLMax + 1] = {};  // FP8: forward / reverse operand-scale undo per layer
   float rsc[kLMax + 1] = {};
 };
@@ -451,7 +452,9 @@ hipError_t launch(const sdf_net* net, const KArgs& a, hipStream_t s) {
 #undef K32
   } else {
     const bool pair = net->prec == SDF_BF16X3;  // points per workgroup, as in the kernel
-    const int64_t pts = k16_points(W, pair ? 2 : 1, net->prec == SDF_FP8);
+    const int var = (MODE == MODE_PROJECT && k16_has_variant(W, net->prec == SDF_BF16 || net->prec == SDF_FP16))
+                        ? net->variant : 0;
+    const int64_t pts = k16_points(W, pair ? 2 : 1, net->prec == SDF_FP8, var);
     dim3 block16(64 * k16_waves(W));
     // a dispatch holds fewer than 2^32 work-items: split very large batches
     const int64_t max_pts = ((int64_t)1 << 22) * pts;
@@ -466,13 +469,20 @@ hipError_t launch(const sdf_net* net, const KArgs& a, hipStream_t s) {
       if (a.hit) c.hit = a.hit + p0;
       dim3 grid((unsigned)((c.n + pts - 1) / pts));
 #define K16(WW, PP) \
-  if (W == WW && net->prec == PP) hipLaunchKernelGGL((sdf_k16<WW, PP, MODE>), grid, block16, 0, s, c);
+  if (W == WW && net->prec == PP && var == 0) hipLaunchKernelGGL((sdf_k16<WW, PP, MODE, 0>), grid, block16, 0, s, c);
       K16(64, PREC_BF16) K16(128, PREC_BF16) K16(256, PREC_BF16)
       K16(64, PREC_FP16) K16(128, PREC_FP16) K16(256, PREC_FP16)
       K16(64, PREC_BF16X3) K16(128, PREC_BF16X3) K16(256, PREC_BF16X3)
       K16(512, PREC_BF16) K16(512, PREC_FP16) K16(512, PREC_BF16X3)
       K16(128, PREC_FP8) K16(256, PREC_FP8) K16(512, PREC_FP8)
 #undef K16
+      if constexpr (MODE == MODE_PROJECT) {
+#define K16V(WW, PP) \
+  if (W == WW && net->prec == PP && var == 1) hipLaunchKernelGGL((sdf_k16<WW, PP, MODE, 1>), grid, block16, 0, s, c);
+        K16V(128, PREC_BF16) K16V(256, PREC_BF16) K16V(512, PREC_BF16)
+        K16V(128, PREC_FP16) K16V(256, PREC_FP16) K16V(512, PREC_FP16)
+#undef K16V
+      }
     }
   }
   return hipGetLastError();
@@ -752,14 +762,88 @@ int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* p
 struct sdf_group {
   int device = 0;
   int prec = 0;
+  int per_network = 0;  // 1: one launch per network instead of one per width (autotuner)
   struct Class {
-    int W = 0, n = 0, tiles = 0;
-    KArgs* d_args = nullptr;  // [n]
-    int* d_start = nullptr;   // [n]
+    int W = 0, n = 0, var = 0;
+    int tiles[2] = {0, 0};         // per tile variant
+    KArgs* d_args = nullptr;       // [n]
+    int* d_start[2] = {nullptr, nullptr};  // [n] per tile variant
   };
   std::vector<Class> classes;
+  std::vector<const sdf_net*> nets;  // members with vertices, class by class
+  std::vector<KArgs> args;           // host copy of the device table, same order
   void* d_mem = nullptr;
 };
+
+namespace {
+
+bool has_variant(int W, int prec) { return k16_has_variant(W, prec == SDF_BF16 || prec == SDF_FP16); }
+
+// One grouped launch for a width class with the given tables and tile variant.
+hipError_t launch_class(int prec, const sdf_group::Class& c, const KArgs* d_args, const int* d_start,
+                        int var, hipStream_t s) {
+  const int tiles = c.tiles[var];
+  const dim3 block(64 * k16_waves(c.W));
+  // a dispatch holds fewer than 2^32 work-items
+  for (int64_t t0 = 0; t0 < tiles; t0 += 1 << 22) {
+    const dim3 grid((unsigned)std::min<int64_t>(1 << 22, tiles - t0));
+#define KG(WW, PP, VV)                                                                               \
+  if (c.W == WW && prec == PP && var == VV)                                                          \
+    hipLaunchKernelGGL((sdf_k16_group<WW, PP, MODE_PROJECT, VV>), grid, block, 0, s, d_args, d_start, \
+                       c.n, (int)t0);
+    KG(64, PREC_BF16, 0) KG(128, PREC_BF16, 0) KG(256, PREC_BF16, 0) KG(512, PREC_BF16, 0)
+    KG(64, PREC_FP16, 0) KG(128, PREC_FP16, 0) KG(256, PREC_FP16, 0) KG(512, PREC_FP16, 0)
+    KG(64, PREC_BF16X3, 0) KG(128, PREC_BF16X3, 0) KG(256, PREC_BF16X3, 0) KG(512, PREC_BF16X3, 0)
+    KG(128, PREC_FP8, 0) KG(256, PREC_FP8, 0) KG(512, PREC_FP8, 0)
+    KG(128, PREC_BF16, 1) KG(256, PREC_BF16, 1) KG(512, PREC_BF16, 1)
+    KG(128, PREC_FP16, 1) KG(256, PREC_FP16, 1) KG(512, PREC_FP16, 1)
+#undef KG
+  }
+  return hipGetLastError();
+}
+
+// A whole pass: every class (grouped) or every network (per network), with the
+// class tables at `d_args`-relative positions of the group (off) or host args.
+hipError_t group_pass(const sdf_group* grp, const KArgs* d_table, const std::vector<KArgs>& host_args,
+                      hipStream_t s) {
+  if (grp->per_network) {
+    for (size_t i = 0; i < grp->nets.size(); ++i) {
+      const hipError_t e = launch<MODE_PROJECT>(grp->nets[i], host_args[i], s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  int off = 0;
+  for (const auto& c : grp->classes) {
+    const hipError_t e = launch_class(grp->prec, c, d_table + off, c.d_start[c.var], c.var, s);
+    if (e != hipSuccess) return e;
+    off += c.n;
+  }
+  return hipSuccess;
+}
+
+// Mean milliseconds of `reps` calls of fn after one warm-up call.
+template <class F>
+float time_ms(F fn, hipStream_t s, int reps) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.0f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.0f;
+  }
+  fn();
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r) fn();
+  (void)hipEventRecord(e1, s);
+  (void)hipEventSynchronize(e1);
+  float ms = -1.0f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -793,13 +877,12 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
   }
   if (prec == SDF_FP32) return fail(SDF_EUNSUPPORTED, "grouped launches run the 16-bit kernels only");
   const bool pair = prec == SDF_BF16X3;
-  auto pts_per_tile = [&](int W) { return k16_points(W, pair ? 2 : 1, prec == SDF_FP8); };
+  auto pts_per_tile = [&](int W, int var) { return k16_points(W, pair ? 2 : 1, prec == SDF_FP8, var); };
 
   sdf_group* grp = new sdf_group();
   grp->device = dev;
   grp->prec = prec;
-  std::vector<KArgs> args;
-  std::vector<int> starts;
+  std::vector<int> starts[2];
   const int widths[4] = {64, 128, 256, 512};
   for (int W : widths) {
     std::vector<int> idx;
@@ -814,7 +897,7 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
     sdf_group::Class c;
     c.W = W;
     c.n = (int)idx.size();
-    int64_t tiles = 0;
+    int64_t tiles[2] = {0, 0};
     for (int i : idx) {
       const sdf_net* net = nets[i];
       KArgs a{};
@@ -828,35 +911,39 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
       a.L = net->L;
       a.skip = net->skip;
       a.ff = net->desc.fourier > 0 ? 1 : 0;
-  a.ff = net->desc.fourier > 0 ? 1 : 0;
       for (int l = 0; l <= kLMax; ++l) {
         a.fsc[l] = net->fsc[l];
         a.rsc[l] = net->rsc[l];
       }
-      starts.push_back((int)tiles);
-      args.push_back(a);
-      tiles += (counts[i] + pts_per_tile(W) - 1) / pts_per_tile(W);
+      for (int v = 0; v < 2; ++v) {
+        starts[v].push_back((int)tiles[v]);
+        tiles[v] += (counts[i] + pts_per_tile(W, v) - 1) / pts_per_tile(W, v);
+      }
+      grp->args.push_back(a);
+      grp->nets.push_back(net);
     }
-    if (tiles > 0x7fffffff) {
+    if (tiles[1] > 0x7fffffff) {
       sdf_group_destroy(grp);
       return fail(SDF_EINVAL, "too many tiles");
     }
-    c.tiles = (int)tiles;
+    c.tiles[0] = (int)tiles[0];
+    c.tiles[1] = (int)tiles[1];
     grp->classes.push_back(c);
   }
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(dev);
-  const size_t abytes = args.size() * sizeof(KArgs), sbytes = starts.size() * sizeof(int);
-  if (!args.empty()) {
-    if (hipMalloc(&grp->d_mem, abytes + sbytes + 256) != hipSuccess) {
+  const size_t abytes = grp->args.size() * sizeof(KArgs), sbytes = starts[0].size() * sizeof(int);
+  if (!grp->args.empty()) {
+    if (hipMalloc(&grp->d_mem, abytes + 2 * sbytes + 256) != hipSuccess) {
       (void)hipSetDevice(prev);
       sdf_group_destroy(grp);
       return fail(SDF_ENOMEM, "hipMalloc(group tables)");
     }
     unsigned char* m = (unsigned char*)grp->d_mem;
-    if (hipMemcpy(m, args.data(), abytes, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(m + abytes, starts.data(), sbytes, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(m, grp->args.data(), abytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m + abytes, starts[0].data(), sbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m + abytes + sbytes, starts[1].data(), sbytes, hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipSetDevice(prev);
       sdf_group_destroy(grp);
       return fail(SDF_EDEVICE, "hipMemcpy(group tables)");
@@ -864,7 +951,8 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
     int off = 0;
     for (auto& c : grp->classes) {
       c.d_args = (KArgs*)m + off;
-      c.d_start = (int*)(m + abytes) + off;
+      c.d_start[0] = (int*)(m + abytes) + off;
+      c.d_start[1] = (int*)(m + abytes + sbytes) + off;
       off += c.n;
     }
   }
@@ -876,29 +964,128 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
 int sdf_group_collide_project(const sdf_group* grp, void* stream) {
   g_err.clear();
   if (!grp) return fail(SDF_EINVAL, "group is NULL");
+  if (grp->classes.empty()) return SDF_OK;
   int prev = 0;
   (void)hipGetDevice(&prev);
   if (prev != grp->device) (void)hipSetDevice(grp->device);
-  const hipStream_t s = (hipStream_t)stream;
-  for (const auto& c : grp->classes) {
-    const dim3 block(64 * k16_waves(c.W));
-    // a dispatch holds fewer than 2^32 work-items
-    for (int64_t t0 = 0; t0 < c.tiles; t0 += 1 << 22) {
-      const dim3 grid((unsigned)std::min<int64_t>(1 << 22, c.tiles - t0));
-#define KG(WW, PP)                                                                                  \
-  if (c.W == WW && grp->prec == PP)                                                                 \
-    hipLaunchKernelGGL((sdf_k16_group<WW, PP, MODE_PROJECT>), grid, block, 0, s, c.d_args, c.d_start, \
-                       c.n, (int)t0);
-      KG(64, PREC_BF16) KG(128, PREC_BF16) KG(256, PREC_BF16) KG(512, PREC_BF16)
-      KG(64, PREC_FP16) KG(128, PREC_FP16) KG(256, PREC_FP16) KG(512, PREC_FP16)
-      KG(64, PREC_BF16X3) KG(128, PREC_BF16X3) KG(256, PREC_BF16X3) KG(512, PREC_BF16X3)
-      KG(128, PREC_FP8) KG(256, PREC_FP8) KG(512, PREC_FP8)
-#undef KG
-    }
-  }
-  const hipError_t e = hipGetLastError();
+  const hipError_t e = group_pass(grp, grp->classes[0].d_args, grp->args, (hipStream_t)stream);
   if (prev != grp->device) (void)hipSetDevice(prev);
   return e == hipSuccess ? SDF_OK : hip_fail(e, "kernel launch");
+}
+
+int sdf_net_autotune(sdf_net* net, int64_t n_sample, void* stream, int* variant) {
+  g_err.clear();
+  if (!net) return fail(SDF_EINVAL, "net is NULL");
+  if (n_sample < 1 || n_sample > ((int64_t)1 << 26)) return fail(SDF_EINVAL, "n_sample must be in [1, 2^26]");
+  if (!has_variant(net->W, net->prec)) {
+    net->variant = 0;
+    if (variant) *variant = 0;
+    return SDF_OK;
+  }
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(net->device);
+  // points spread over [-1, 1]^3 (a fixed linear congruential sequence)
+  std::vector<float> h((size_t)n_sample * 3);
+  uint32_t st = 12345u;
+  for (auto& v : h) {
+    st = st * 1664525u + 1013904223u;
+    v = (float)((st >> 8) * (2.0 / 16777216.0) - 1.0);
+  }
+  float* d = nullptr;
+  if (hipMalloc(&d, h.size() * 4) != hipSuccess) {
+    (void)hipSetDevice(prev);
+    return fail(SDF_ENOMEM, "hipMalloc(autotune sample)");
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  float best = 0.0f;
+  int pick = 0;
+  for (int v = 0; v < 2; ++v) {
+    if (hipMemcpy(d, h.data(), h.size() * 4, hipMemcpyHostToDevice) != hipSuccess) break;
+    net->variant = v;
+    const float ms = time_ms([&] { (void)run<MODE_PROJECT>(net, d, d, n_sample, 0.005f, nullptr, nullptr, nullptr, nullptr, s); }, s, 5);
+    if (ms > 0.0f && (v == 0 || ms < best)) {
+      best = ms;
+      pick = v;
+    }
+  }
+  net->variant = pick;
+  (void)hipFree(d);
+  (void)hipSetDevice(prev);
+  if (variant) *variant = pick;
+  return SDF_OK;
+}
+
+int sdf_net_set_tile_variant(sdf_net* net, int variant) {
+  g_err.clear();
+  if (!net) return fail(SDF_EINVAL, "net is NULL");
+  if (variant != 0 && variant != 1) return fail(SDF_EINVAL, "variant must be 0 or 1");
+  if (variant == 1 && !has_variant(net->W, net->prec))
+    return fail(SDF_EUNSUPPORTED, "this network has one tile variant");
+  net->variant = variant;
+  return SDF_OK;
+}
+
+int sdf_group_autotune(sdf_group* grp, void* stream, int* per_network) {
+  g_err.clear();
+  if (!grp) return fail(SDF_EINVAL, "group is NULL");
+  if (grp->classes.empty()) return SDF_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(grp->device);
+  const hipStream_t s = (hipStream_t)stream;
+  // scratch copies of every vertex buffer, so the members' vertices are not moved
+  int64_t total = 0;
+  for (const auto& a : grp->args) total += a.n;
+  float* scratch = nullptr;
+  KArgs* d_tab = nullptr;
+  const size_t tab_bytes = grp->args.size() * sizeof(KArgs);
+  if (hipMalloc(&scratch, (size_t)total * 12 + 16) != hipSuccess || hipMalloc(&d_tab, tab_bytes) != hipSuccess) {
+    if (scratch) (void)hipFree(scratch);
+    (void)hipSetDevice(prev);
+    return fail(SDF_ENOMEM, "hipMalloc(autotune scratch)");
+  }
+  std::vector<KArgs> tmp = grp->args;
+  int64_t o = 0;
+  for (auto& a : tmp) {
+    a.pts_in = a.pts_out = scratch + 3 * o;
+    o += a.n;
+  }
+  auto refill = [&] {  // the members' vertices, fresh for every timing
+    int64_t q = 0;
+    for (const auto& a : grp->args) {
+      (void)hipMemcpyAsync(scratch + 3 * q, a.pts_in, (size_t)a.n * 12, hipMemcpyDeviceToDevice, s);
+      q += a.n;
+    }
+  };
+  hipError_t e = hipMemcpy(d_tab, tmp.data(), tab_bytes, hipMemcpyHostToDevice);
+  // 1) tile variant per width class
+  int off = 0;
+  for (auto& c : grp->classes) {
+    if (has_variant(c.W, grp->prec)) {
+      float t[2];
+      for (int v = 0; v < 2; ++v) {
+        refill();
+        t[v] = time_ms([&] { (void)launch_class(grp->prec, c, d_tab + off, c.d_start[v], v, s); }, s, 3);
+      }
+      c.var = (t[1] > 0.0f && t[1] < t[0]) ? 1 : 0;
+    }
+    off += c.n;
+  }
+  // 2) one launch per width class, or one per network (networks keep their own variant)
+  float t[2];
+  for (int m = 0; m < 2; ++m) {
+    grp->per_network = m;
+    refill();
+    t[m] = time_ms([&] { (void)group_pass(grp, d_tab, tmp, s); }, s, 3);
+  }
+  grp->per_network = (t[1] > 0.0f && t[1] < t[0]) ? 1 : 0;
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(scratch);
+  (void)hipFree(d_tab);
+  (void)hipSetDevice(prev);
+  if (per_network) *per_network = grp->per_network;
+  return e == hipSuccess ? SDF_OK : hip_fail(e, "autotune");
 }
 
 }  // extern "C"

@@ -36,17 +36,17 @@ namespace sdfc {
 // NS = 1: plain 16-bit operands.  NS = 2: every operand is carried as a BF16
 // pair hi + lo (lo = bf16(v - hi)) and each product is hi*hi + lo*hi + hi*lo,
 // which keeps about 16 significant bits (compensated "BF16x3").
-template <int W, int NS, bool F8 = false>
+template <int W, int NS, bool F8 = false, int VAR = 0>
 struct GeoB {
   static constexpr int NWV = k16_waves(W);    // waves per workgroup
-  static constexpr int NCT = k16_cols(W, NS, F8);  // column tiles of 16 points
+  static constexpr int NCT = k16_cols(W, NS, F8, VAR);  // column tiles of 16 points
   static constexpr int PTS = 16 * NCT;         // points per workgroup
   static constexpr int FW = W / NWV;           // features per wave
   static constexpr int MTW = FW / 16;          // M-tiles per wave
   static constexpr int KM = F8 ? 128 : 32;      // K per MFMA
   static constexpr int KB = W / KM;            // K-blocks per layer
   static constexpr int FRAG = F8 ? 2 * kFrag : kFrag;  // bytes of one operand fragment
-  static constexpr int DMAX = W == 512 ? (F8 ? 2 : 1) : (NS == 2 ? 2 : SDF_K16_D);
+  static constexpr int DMAX = (W == 512 ? (F8 ? 2 : 1) : (NS == 2 ? 2 : SDF_K16_D)) * (VAR == 1 ? 2 : 1);
   static constexpr int D = KB < DMAX ? KB : DMAX;  // weight prefetch depth in K-steps
   // r_1..r_LS of the stack live in LDS (the reverse sweep reads them last);
   // the rest stay in registers.
@@ -95,7 +95,7 @@ __device__ __forceinline__ void split4(f32x4 v, uint2& hi, uint2& lo) {
 
 // The whole per-workgroup pass over tile `tile` (points [tile PTS, tile PTS +
 // PTS) of a.pts_in) of network `a`.
-template <int W, int PREC, int MODE>
+template <int W, int PREC, int MODE, int VAR>
 __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   constexpr int NS = PREC == PREC_BF16X3 ? 2 : 1;
   // FP8: E4M3 exchange operands (forward activations stored as r / 4), weights
@@ -103,7 +103,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   // for the reverse sweep stays BF16.
   constexpr bool F8 = PREC == PREC_FP8;
   constexpr int OP = (PREC == PREC_BF16X3 || F8) ? PREC_BF16 : PREC;  // 16-bit operand / stack type
-  using G = GeoB<W, NS, F8>;
+  using G = GeoB<W, NS, F8, VAR>;
   using AT = std::conditional_t<F8, u32x8, u32x4>;  // one lane's share of an operand fragment
   constexpr int NWV = G::NWV, NT = 64 * NWV;
   constexpr SmallLayout SL{W};
@@ -548,14 +548,14 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
 #define K16_WG_SIZE(W) \
   __attribute__((amdgpu_flat_work_group_size(64 * k16_waves(W), 64 * k16_waves(W)), amdgpu_waves_per_eu(2)))
 
-template <int W, int PREC, int MODE>
+template <int W, int PREC, int MODE, int VAR>
 __global__ void K16_WG_SIZE(W) sdf_k16(const KArgs a) {
-  k16_tile<W, PREC, MODE>(a, blockIdx.x);
+  k16_tile<W, PREC, MODE, VAR>(a, blockIdx.x);
 }
 
 // Several networks of one width in one launch: workgroup b runs tile
 // b - tile_start[i] of network i, where tile_start[i] <= b < tile_start[i+1].
-template <int W, int PREC, int MODE>
+template <int W, int PREC, int MODE, int VAR>
 __global__ void K16_WG_SIZE(W) sdf_k16_group(const KArgs* __restrict__ nets,
                                              const int* __restrict__ tile_start, int n_nets,
                                              int tile0) {
@@ -566,12 +566,13 @@ __global__ void K16_WG_SIZE(W) sdf_k16_group(const KArgs* __restrict__ nets,
     if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
   }
   const int i = __builtin_amdgcn_readfirstlane(lo);
-  k16_tile<W, PREC, MODE>(nets[i], b - tile_start[i]);
+  k16_tile<W, PREC, MODE, VAR>(nets[i], b - tile_start[i]);
 }
 
-#define SDF_K16_INST(W, PREC, MODE) \
-  template __global__ void sdf_k16<W, PREC, MODE>(const KArgs); \
-  template __global__ void sdf_k16_group<W, PREC, MODE>(const KArgs*, const int*, int, int);
+#define SDF_K16_INST_V(W, PREC, MODE, VAR) \
+  template __global__ void sdf_k16<W, PREC, MODE, VAR>(const KArgs); \
+  template __global__ void sdf_k16_group<W, PREC, MODE, VAR>(const KArgs*, const int*, int, int);
+#define SDF_K16_INST(W, PREC, MODE) SDF_K16_INST_V(W, PREC, MODE, 0)
 #define SDF_K16_MODES(W, PREC) \
   SDF_K16_INST(W, PREC, MODE_QUERY) SDF_K16_INST(W, PREC, MODE_GRAD) SDF_K16_INST(W, PREC, MODE_PROJECT)
 #define SDF_K16_PRECS(W) \
@@ -583,5 +584,12 @@ SDF_K16_PRECS(512)
 SDF_K16_MODES(128, PREC_FP8)
 SDF_K16_MODES(256, PREC_FP8)
 SDF_K16_MODES(512, PREC_FP8)
+// tile variant 1 for the autotuner
+SDF_K16_INST_V(128, PREC_BF16, MODE_PROJECT, 1)
+SDF_K16_INST_V(256, PREC_BF16, MODE_PROJECT, 1)
+SDF_K16_INST_V(512, PREC_BF16, MODE_PROJECT, 1)
+SDF_K16_INST_V(128, PREC_FP16, MODE_PROJECT, 1)
+SDF_K16_INST_V(256, PREC_FP16, MODE_PROJECT, 1)
+SDF_K16_INST_V(512, PREC_FP16, MODE_PROJECT, 1)
 
 }  // namespace sdfc

@@ -56,10 +56,19 @@ __host__ __device__ constexpr int k16_waves(int W) { return W >= 128 ? 8 : 4; }
 #ifndef SDF_K16_COLS256
 #define SDF_K16_COLS256 4
 #endif
-__host__ __device__ constexpr int k16_cols(int W, int NS, bool f8 = false) {
-  return W == 512 ? ((NS == 1 && !f8) ? 2 : 1) : (NS == 1 ? (W == 256 ? SDF_K16_COLS256 : 4) : 2);
+// Tile variant 1 (plain 16-bit collide_project at widths 128-512, picked by
+// the autotuner): half the points of variant 0 and twice its weight-prefetch
+// depth.
+__host__ __device__ constexpr int k16_cols(int W, int NS, bool f8 = false, int var = 0) {
+  const int c = W == 512 ? ((NS == 1 && !f8) ? 2 : 1) : (NS == 1 ? (W == 256 ? SDF_K16_COLS256 : 4) : 2);
+  return var == 1 && c > 1 ? c / 2 : c;
 }
-__host__ __device__ constexpr int k16_points(int W, int NS, bool f8 = false) { return 16 * k16_cols(W, NS, f8); }
+__host__ __device__ constexpr int k16_points(int W, int NS, bool f8 = false, int var = 0) {
+  return 16 * k16_cols(W, NS, f8, var);
+}
+__host__ __device__ constexpr bool k16_has_variant(int W, int prec_16bit_plain) {
+  return W >= 128 && prec_16bit_plain;
+}
 
 // Fragment geometry of one hidden layer.
 //  16-bit (v_mfma_f32_16x16x32_{bf16,f16}): M-tiles of 16 output rows, K-blocks

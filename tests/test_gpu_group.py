@@ -134,3 +134,40 @@ def test_graph_of_thirty_passes_replays_exactly():
     ge.close()
     for n in nets:
         n.close()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_tile_variants_and_autotune_keep_the_bits(precision):
+    """The autotuner's choices (tile variant per network or width class, grouped
+    or per-network launches) change timing only: every configuration produces
+    the same bits as the default one."""
+    cs = small_set(n_nets=8, total=80_000)
+    nets = [B.SdfNet(c["spec"], c["params"], precision) for c in cs]
+    X0 = [torch.from_numpy(np.ascontiguousarray(c["points"], np.float32)).cuda() for c in cs]
+    ref = [x.clone() for x in X0]
+    for net, x in zip(nets, ref):
+        net.collide_project(x, EPS, want=())
+    for v in (1, 0):
+        for net, x0, r in zip(nets, X0, ref):
+            x = x0.clone()
+            net.set_tile_variant(v)
+            net.collide_project(x, EPS, want=())
+            torch.cuda.synchronize()
+            assert torch.equal(x, r), "variant %d differs" % v
+    Xg = [x.clone() for x in X0]
+    grp = B.SdfGroup(nets, Xg, EPS)
+    per_net = grp.autotune()
+    torch.cuda.synchronize()
+    for a, b in zip(Xg, X0):  # autotuning works on copies
+        assert torch.equal(a, b)
+    grp.collide_project()
+    torch.cuda.synchronize()
+    for a, r in zip(Xg, ref):
+        assert torch.equal(a, r)
+    print(json.dumps({"test": "autotune", "precision": precision, "per_network": per_net,
+                      "variants": [n.autotune(n_sample=1 << 16) for n in nets[:3]]}), flush=True)
+    with pytest.raises(B.SdfError):
+        nets[0].set_tile_variant(2)
+    grp.close()
+    for n in nets:
+        n.close()

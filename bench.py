@@ -245,7 +245,7 @@ def main():
         copy_probe(args.copy_probe_mib)
         return
     if args.traffic_from:
-        traffic_record(*args.traffic_from, kernel="sdf_k16<256, %d, 2>" % {"bf16": 1, "fp16": 2, "bf16x3": 3}[
+        traffic_record(*args.traffic_from, kernel="sdf_k16<256, %d, 2, 0>" % {"bf16": 1, "fp16": 2, "bf16x3": 3, "fp8": 4}[
             args.precision], precision=args.precision, out=TRAFFIC_FILE,
             copy_mib=args.copy_mib)
         return

@@ -41,6 +41,7 @@ struct sdf_net {
   float* d_scratch = nullptr;  // FP32 sigma stack, one slot per resident workgroup
   int slots = 0;
   int variant = 0;            // tile variant of the 16-bit collide_project kernel (autotuner)
+  float c_l1g = 0.0f, c_skg = 0.0f, c_wob = 0.0f;  // see KArgs
   float fsc[kLMax + 1] = {};  // FP8: forward / reverse operand-scale undo per layer
   float rsc[kLMax + 1] = {};
 };
@@ -395,6 +396,9 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
   net->prec = prec;
   net->bo = n.bo;
   net->stream_bytes = stream.size();
+  net->c_l1g = (float)(std::ldexp(1.0, -S[1]) / kappa);
+  net->c_skg = skip ? (float)(std::ldexp(1.0, -S[skip]) / (kappa * facc(skip))) : 0.0f;
+  net->c_wob = (float)(kappa * std::ldexp(1.0, S[L]));
   for (int l = 0; l <= kLMax; ++l) {
     net->fsc[l] = (prec == SDF_FP8 && l >= 2 && l <= L) ? (float)std::ldexp(1.0, 2 - sf[l]) : 1.0f;
     net->rsc[l] = (prec == SDF_FP8 && l >= 2 && l <= L) ? (float)std::ldexp(1.0, -sr[l]) : 1.0f;
@@ -552,6 +556,9 @@ int run(const sdf_net* net, const float* pts_in, float* pts_out, int64_t n, floa
   a.L = net->L;
   a.skip = net->skip;
   a.ff = net->desc.fourier > 0 ? 1 : 0;
+  a.c_l1g = net->c_l1g;
+  a.c_skg = net->c_skg;
+  a.c_wob = net->c_wob;
   a.nch = (net->L - 1) * net->chunks_per_layer * (MODE == MODE_QUERY ? 1 : 2);
   a.ntiles = (int)tiles;
   int prev = 0;
@@ -911,6 +918,9 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
       a.L = net->L;
       a.skip = net->skip;
       a.ff = net->desc.fourier > 0 ? 1 : 0;
+      a.c_l1g = net->c_l1g;
+      a.c_skg = net->c_skg;
+      a.c_wob = net->c_wob;
       for (int l = 0; l <= kLMax; ++l) {
         a.fsc[l] = net->fsc[l];
         a.rsc[l] = net->rsc[l];

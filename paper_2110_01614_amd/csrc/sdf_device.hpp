@@ -37,6 +37,9 @@ struct KArgs {
   int L;                 // hidden layers
   int skip;              // 0 or 2..L
   int ff;                // 1: Fourier-feature input (layer 1 is an MFMA layer over gamma(x))
+  // 16-bit kernels: the gradient copies of the layer-1 weights and of the skip
+  // x-columns, and the reverse-sweep seed, as multiples of their forward copies
+  float c_l1g, c_skg, c_wob;
   int nch;               // chunks streamed per tile
   int ntiles;            // ceil(n / 64)
   // fitting (MODE_TRAIN) only: per-point targets and the per-chunk workspace

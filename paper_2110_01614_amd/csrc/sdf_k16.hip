@@ -27,6 +27,9 @@
 #define SDF_K16_D 1
 #endif
 
+#ifndef SDF_K16_SCHED
+#define SDF_K16_SCHED 1
+#endif
 #ifndef SDF_K16_OWN
 #define SDF_K16_OWN 1
 #endif
@@ -48,15 +51,20 @@ struct GeoB {
   static constexpr int FRAG = F8 ? 2 * kFrag : kFrag;  // bytes of one operand fragment
   static constexpr int DMAX = (W == 512 ? (F8 ? 2 : 1) : (NS == 2 ? 2 : SDF_K16_D)) * (VAR == 1 ? 2 : 1);
   static constexpr int D = KB < DMAX ? KB : DMAX;  // weight prefetch depth in K-steps
+  // ring of weight fragments: step j uses slot j % R while step j + R - 1 is
+  // loaded into its own slot; R divides KB so the slots line up across layers
+  static constexpr int R0 = (D + 1) >= 8 ? 8 : (D + 1) >= 4 ? 4 : (D + 1) >= 2 ? 2 : 1;  // power of two
+  static constexpr int R = R0 <= KB ? R0 : KB;
+  static_assert((R & (R - 1)) == 0, "ring size");
   // r_1..r_LS of the stack live in LDS (the reverse sweep reads them last);
   // the rest stay in registers.
-  static constexpr int LS = W >= 256 ? 1 : 0;
+  static constexpr int LS = W == 256 ? 2 : (W > 256 ? 1 : 0);
   static constexpr int STK_BYTES = (LS > 0 ? LS : 1) * NWV * MTW * NCT * NS * 64 * 8;
   static constexpr int WAVE_BYTES = KB * MTW * NS * FRAG;  // one wave's slice of a layer
   static constexpr int LAYER_BYTES = NWV * WAVE_BYTES;
   static constexpr int ACT_BYTES = KB * NCT * FRAG;        // one exchange buffer part
   static constexpr int NS_ = NS;
-  static_assert(MTW >= 1 && KB >= 1 && KB % D == 0, "shape");
+  static_assert(MTW >= 1 && KB >= 1 && KB % R == 0, "shape");
 };
 
 template <int PREC>
@@ -107,10 +115,16 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   using AT = std::conditional_t<F8, u32x8, u32x4>;  // one lane's share of an operand fragment
   constexpr int NWV = G::NWV, NT = 64 * NWV;
   constexpr SmallLayout SL{W};
-  constexpr int MTW = G::MTW, KB = G::KB, NCT = G::NCT, D = G::D, PTS = G::PTS;
+  constexpr int MTW = G::MTW, KB = G::KB, NCT = G::NCT, R = G::R, PTS = G::PTS;
 
   __shared__ __attribute__((aligned(16))) unsigned char act[2][NS][G::ACT_BYTES];
-  __shared__ __attribute__((aligned(16))) float sm[SL.floats()];
+  // The small FP32 block in the compact form this kernel reads: [l1: 4W |
+  // skf: 4W | wof: W | bias of layers 1..8: 8W]; the gradient copies of l1 and
+  // skf and the reverse seed are these times per-network scalars (a.c_l1g,
+  // a.c_skg, a.c_wob).  Layer 1's bias slot holds the Fourier net's bias.
+  constexpr int C_L1 = 0, C_SKF = 4 * W, C_WOF = 8 * W, C_FLOATS = 17 * W;
+  auto c_bias = [](int l) { return 9 * W + (l - 1) * W; };
+  __shared__ __attribute__((aligned(16))) float sm[C_FLOATS];
   __shared__ __attribute__((aligned(16))) f32x4 xs[PTS];  // the workgroup's points
   __shared__ __attribute__((aligned(16))) uint2 stk_lds[G::STK_BYTES / 8];
   __shared__ __attribute__((aligned(16))) f32x4 red[NWV][PTS];  // per wave: f, grad x partials
@@ -139,8 +153,19 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     }
     xs[tid] = v;
   }
-  for (int i = tid; i < SL.floats() / 4; i += NT)
-    reinterpret_cast<f32x4*>(sm)[i] = reinterpret_cast<const f32x4*>(a.small)[i];
+  {
+    const f32x4* src = reinterpret_cast<const f32x4*>(a.small);
+    f32x4* dst = reinterpret_cast<f32x4*>(sm);
+    for (int i = tid; i < W; i += NT) {  // l1, skf: one float4 per feature
+      dst[C_L1 / 4 + i] = src[SL.l1() / 4 + i];
+      dst[C_SKF / 4 + i] = src[SL.skf() / 4 + i];
+    }
+    for (int i = tid; i < W / 4; i += NT) {  // wof, layer-1 bias (Fourier), biases 2..8
+      dst[C_WOF / 4 + i] = src[SL.wof() / 4 + i];
+      dst[c_bias(1) / 4 + i] = src[SL.l1g() / 4 + i];
+    }
+    for (int i = tid; i < (kLMax - 1) * W / 4; i += NT) dst[c_bias(2) / 4 + i] = src[SL.bias(2) / 4 + i];
+  }
 
 
   // feature index of (local M-tile mt, lane group g, element i)
@@ -160,9 +185,9 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   u32x4 ownB[NOWN > 0 ? NOWN : 1][NCT][NS];
 
   // first weight fragments (forward layer 2), in the wave's K-block order
-  AT Aq[D][MTW][NS];
+  AT Aq[R][MTW][NS];
 #pragma unroll
-  for (int s = 0; s < D; ++s)
+  for (int s = 0; s < R - 1; ++s)
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
@@ -250,7 +275,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     for (int mt = 0; mt < MTW; ++mt) {
       f32x4 w4[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) w4[i] = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * feat(mt, i)]);
+      for (int i = 0; i < 4; ++i) w4[i] = *reinterpret_cast<const f32x4*>(&sm[C_L1 + 4 * feat(mt, i)]);
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) {
         const f32x4 x = xs[16 * ct + col];
@@ -268,7 +293,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     for (int mt = 0; mt < MTW; ++mt) {
       f32x4 b4[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) b4[i] = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * feat(mt, i)]);
+      for (int i = 0; i < 4; ++i) b4[i] = *reinterpret_cast<const f32x4*>(&sm[C_L1 + 4 * feat(mt, i)]);
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) {
         const f32x4 x = xs[16 * ct + col];
@@ -285,29 +310,30 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   // wave's own rows form whole K-blocks (OWN), those come first, straight from
   // the registers `put` filled, and are issued before the workgroup barrier
   // that publishes the other waves' rows, so they run while the barrier
-  // resolves and the first LDS reads are in flight.  The next layer's first D
-  // weight K-steps are prefetched from `next` (nullptr: nothing follows).
+  // resolves and the first LDS reads are in flight.  Each step first issues
+  // the loads of later steps (weights R - 1 steps ahead, the next layer's from
+  // `next` (nullptr: nothing follows); activations one step ahead), then its
+  // MFMAs; a scheduling barrier keeps the loads ahead of the MFMAs.
   auto contract = [&](f32x4 (&acc)[MTW][NCT], const unsigned char* in, const unsigned char* layer,
                       const unsigned char* next) {
     auto kbi = [&](int j) { return (kb0 + j) & (KB - 1); };
-    auto step = [&](int j, const AT (&B)[NCT][NS]) {
-      AT Acur[MTW][NS];
-#pragma unroll
-      for (int mt = 0; mt < MTW; ++mt)
-#pragma unroll
-        for (int ps = 0; ps < NS; ++ps) Acur[mt][ps] = Aq[j % D][mt][ps];
-      const int nk = j + D;
+    // weights of step j + R - 1 into their ring slot
+    auto prefetchA = [&](int j) {
+      const int nk = j + R - 1;
       if (nk < KB) {
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-          for (int ps = 0; ps < NS; ++ps) Aq[j % D][mt][ps] = *wfrag<G, AT>(layer, wave, kbi(nk), mt, ps, lane);
+          for (int ps = 0; ps < NS; ++ps) Aq[nk % R][mt][ps] = *wfrag<G, AT>(layer, wave, kbi(nk), mt, ps, lane);
       } else if (next) {
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-          for (int ps = 0; ps < NS; ++ps) Aq[j % D][mt][ps] = *wfrag<G, AT>(next, wave, kbi(nk - KB), mt, ps, lane);
+          for (int ps = 0; ps < NS; ++ps) Aq[nk % R][mt][ps] = *wfrag<G, AT>(next, wave, kbi(nk - KB), mt, ps, lane);
       }
+    };
+    auto step = [&](int j, const AT (&B)[NCT][NS]) {
+      const auto& Acur = Aq[j % R];
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
@@ -325,7 +351,10 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     };
     if constexpr (NOWN > 0)
 #pragma unroll
-      for (int j = 0; j < NOWN; ++j) step(j, ownB[j]);
+      for (int j = 0; j < NOWN; ++j) {
+        prefetchA(j);
+        step(j, ownB[j]);
+      }
     lds_barrier();
     AT Bv[2][NCT][NS];  // B operands of K-steps j (in use) and j + 1 (in flight)
     auto loadB = [&](AT (&dst)[NCT][NS], int j) {
@@ -339,7 +368,9 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     loadB(Bv[0], NOWN);
 #pragma unroll
     for (int j = NOWN; j < KB; ++j) {
+      prefetchA(j);
       if (j + 1 < KB) loadB(Bv[(j + 1 - NOWN) & 1], j + 1);
+      if constexpr (SDF_K16_SCHED) __builtin_amdgcn_sched_barrier(0);
       step(j, Bv[(j - NOWN) & 1]);
     }
   };
@@ -358,8 +389,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     f32x4 acc[MTW][NCT];
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
-      const int boff = (l == 1) ? SL.l1g() : SL.bias(l);  // layer 1: Fourier input only
-      const f32x4 b = *reinterpret_cast<const f32x4*>(&sm[boff + 16 * (MTW * wave + mt) + 4 * g]);
+      const f32x4 b = *reinterpret_cast<const f32x4*>(&sm[c_bias(l) + 16 * (MTW * wave + mt) + 4 * g]);
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[mt][ct] = b;
     }
@@ -368,7 +398,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
       for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[SL.skf() + 4 * feat(mt, i)]);
+          const f32x4 w = *reinterpret_cast<const f32x4*>(&sm[C_SKF + 4 * feat(mt, i)]);
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
             const f32x4 x = xs[16 * ct + col];
@@ -397,12 +427,12 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
         for (int ct = 0; ct < NCT; ++ct) part[ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt) {
-          const f32x4 wf = *reinterpret_cast<const f32x4*>(&sm[SL.wof() + 16 * (MTW * wave + mt) + 4 * g]);
-          const f32x4 wb = *reinterpret_cast<const f32x4*>(&sm[SL.wob() + 16 * (MTW * wave + mt) + 4 * g]);
+          const f32x4 wf = *reinterpret_cast<const f32x4*>(&sm[C_WOF + 16 * (MTW * wave + mt) + 4 * g]);
+          const f32x4 wb = wf * a.c_wob;
           f32x4 wg[4];
           if constexpr (decltype(SKIPG)::value)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) wg[i] = *reinterpret_cast<const f32x4*>(&sm[SL.skg() + 4 * feat(mt, i)]);
+            for (int i = 0; i < 4; ++i) wg[i] = *reinterpret_cast<const f32x4*>(&sm[C_SKF + 4 * feat(mt, i)]) * a.c_skg;
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
             f32x4 d;
@@ -461,9 +491,10 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
         for (int mt = 0; mt < MTW; ++mt) {
           f32x4 wg[4];
           if constexpr (decltype(TOX)::value) {
-            const int off = (l == 2) ? SL.l1g() : SL.skg();
+            const int off = (l == 2) ? C_L1 : C_SKF;
+            const float c = (l == 2) ? a.c_l1g : a.c_skg;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) wg[i] = *reinterpret_cast<const f32x4*>(&sm[off + 4 * feat(mt, i)]);
+            for (int i = 0; i < 4; ++i) wg[i] = *reinterpret_cast<const f32x4*>(&sm[off + 4 * feat(mt, i)]) * c;
           }
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
@@ -503,7 +534,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
         for (int mt = 0; mt < MTW; ++mt) {
           f32x4 b4[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) b4[i] = *reinterpret_cast<const f32x4*>(&sm[SL.l1() + 4 * feat(mt, i)]);
+          for (int i = 0; i < 4; ++i) b4[i] = *reinterpret_cast<const f32x4*>(&sm[C_L1 + 4 * feat(mt, i)]);
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
             const f32x4 x = xs[16 * ct + col];

@@ -184,6 +184,18 @@ int sdf_net_autotune(sdf_net* net, int64_t n_sample, void* stream, int* variant)
 int sdf_net_set_tile_variant(sdf_net* net, int variant);
 int sdf_group_autotune(sdf_group* grp, void* stream, int* per_network);
 
+/* ---- the time step between collision passes (Sec. 4.1: explicit Verlet) ----
+ *
+ * In place on device float32 [n][3] arrays: pts <- pts + (1 - damping)
+ * (pts - prev) + gravity dt^2 (the multiply-add rounded once), prev <- the old
+ * pts.  gravity: HOST float[3].  Gravity only: the cloth's internal forces are
+ * not part of the collision path.  With sdf_group_collide_project after it,
+ * one simulation step is two launches that a HIP graph can capture.
+ * Errors: SDF_EINVAL for bad sizes, non-finite values, NULL, misaligned or
+ * identical buffers. */
+int sdf_verlet_step(float* pts, float* prev, int64_t n, float dt, const float* gravity, float damping,
+                    void* stream);
+
 /* ---- fitting (Sec. 3.1): MLP regressed onto sampled signed distances ---- */
 
 /* Device workspace bytes sdf_train_step needs for a batch of n points with

@@ -75,6 +75,8 @@ def _load():
     lib.sdf_net_set_tile_variant.argtypes = [vp, ctypes.c_int]
     lib.sdf_group_autotune.restype = ctypes.c_int
     lib.sdf_group_autotune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int)]
+    lib.sdf_verlet_step.restype = ctypes.c_int
+    lib.sdf_verlet_step.argtypes = [vp, vp, i64, f32, ctypes.POINTER(ctypes.c_float), f32, vp]
     lib.sdf_group_destroy.restype = ctypes.c_int
     lib.sdf_group_destroy.argtypes = [vp]
     lib.sdf_train_workspace_bytes.restype = i64
@@ -349,6 +351,18 @@ def sdf_group_autotune(group, stream=None) -> int:
     v = ctypes.c_int(0)
     _check(lib.sdf_group_autotune(group, _stream(stream), ctypes.byref(v)))
     return v.value
+
+
+def verlet_step(pts, prev, dt, gravity=(0.0, 0.0, -9.81), damping=0.0, stream=None):
+    """One explicit-Verlet step of the vertex tensors (in place; both [n, 3] float32 CUDA)."""
+    import numpy as np
+    g = np.ascontiguousarray(gravity, dtype=np.float32).reshape(3)
+    SdfNet._pts(pts)
+    SdfNet._pts(prev)
+    if pts.shape != prev.shape:
+        raise ValueError("pts and prev must have the same shape")
+    _check(lib.sdf_verlet_step(_ptr(pts), _ptr(prev), pts.shape[0], float(dt),
+                               g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), float(damping), _stream(stream)))
 
 
 class SdfGroup:

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdfcollide.so")
-SOURCES = ["sdf_api.cpp", "sdf_k16.hip", "sdf_k32.hip", "sdf_train.hip"]
+SOURCES = ["sdf_api.cpp", "sdf_k16.hip", "sdf_k32.hip", "sdf_train.hip", "sdf_step.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -21,6 +21,7 @@ __global__ void sdf_k16_group(const KArgs* nets, const int* tile_start, int n_ne
 template <int W, int MODE>
 __global__ void sdf_k32(const KArgs a);
 __global__ void pack_fp32_kernel(TrainNet t, const float* P, float* stream, float* small);
+__global__ void verlet_kernel(float* x, float* xp, int64_t m, float k, float c0, float c1, float c2);
 __global__ void fill_kernel(float* p, int64_t n, float v);
 __global__ void loss_reduce_kernel(const float* terms, int64_t n, float* loss);
 __global__ void wgrad_kernel(TrainNet t, const float* E, const float* H, const float* U, int64_t n,
@@ -1096,6 +1097,25 @@ int sdf_group_autotune(sdf_group* grp, void* stream, int* per_network) {
   (void)hipSetDevice(prev);
   if (per_network) *per_network = grp->per_network;
   return e == hipSuccess ? SDF_OK : hip_fail(e, "autotune");
+}
+
+int sdf_verlet_step(float* pts, float* prev, int64_t n, float dt, const float* gravity, float damping,
+                    void* stream) {
+  g_err.clear();
+  if (n < 0) return fail(SDF_EINVAL, "n < 0");
+  if (!std::isfinite(dt) || !std::isfinite(damping) || !gravity) return fail(SDF_EINVAL, "bad dt, damping or gravity");
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(gravity[c])) return fail(SDF_EINVAL, "gravity must be finite");
+  if (n == 0) return SDF_OK;
+  if (!pts || !prev || !aligned4(pts) || !aligned4(prev)) return fail(SDF_EINVAL, "bad vertex buffers");
+  if (pts == prev) return fail(SDF_EINVAL, "pts and prev must differ");
+  const int64_t m = 3 * n;
+  const double dt2 = (double)dt * (double)dt;
+  const unsigned blocks = (unsigned)std::min<int64_t>((m + 255) / 256, 1 << 16);
+  hipLaunchKernelGGL(verlet_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, pts, prev, m,
+                     1.0f - damping, (float)(gravity[0] * dt2), (float)(gravity[1] * dt2), (float)(gravity[2] * dt2));
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SDF_OK : hip_fail(e, "kernel launch");
 }
 
 }  // extern "C"

@@ -35,11 +35,37 @@ class SdfError(RuntimeError):
         self.code = code
 
 
+def _hip_runtimes_mapped():
+    """Distinct files of the HIP runtime (libamdhip64) mapped into this process."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                path = line.split()[-1] if "/" in line else ""
+                if os.path.basename(path).startswith("libamdhip64.so"):
+                    found.add(os.path.realpath(path))
+    except OSError:
+        pass
+    return found
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsdfcollide.so is not built (run paper_2110_01614_amd.build); "
                           "there is no fallback implementation")
+    # PyTorch supplies device memory and streams, so the library must share its
+    # HIP runtime.  torch ships its own libamdhip64 (soname libamdhip64.so.7)
+    # and its libraries ask for it by another name; if this library were loaded
+    # first, the system copy it needs would come in under that soname and torch
+    # would then map its own copy beside it -- two runtimes, and the second one
+    # to initialise sees no device.  Loading torch first makes this library's
+    # dependency resolve to the runtime already in the process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes_mapped()
+    if len(runtimes) > 1:
+        raise ImportError("more than one HIP runtime is mapped into this process (%s); load "
+                          "libsdfcollide.so only after torch" % ", ".join(sorted(runtimes)))
     vp, i64, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_float
     desc_p = ctypes.POINTER(sdf_net_desc)
     lib.sdf_param_count.restype = i64

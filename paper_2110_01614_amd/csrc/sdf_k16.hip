@@ -608,19 +608,73 @@ __global__ void K16_WG_SIZE(W) sdf_k16_group(const KArgs* __restrict__ nets,
   SDF_K16_INST(W, PREC, MODE_QUERY) SDF_K16_INST(W, PREC, MODE_GRAD) SDF_K16_INST(W, PREC, MODE_PROJECT)
 #define SDF_K16_PRECS(W) \
   SDF_K16_MODES(W, PREC_BF16) SDF_K16_MODES(W, PREC_FP16) SDF_K16_MODES(W, PREC_BF16X3)
-SDF_K16_PRECS(64)
-SDF_K16_PRECS(128)
-SDF_K16_PRECS(256)
-SDF_K16_PRECS(512)
-SDF_K16_MODES(128, PREC_FP8)
-SDF_K16_MODES(256, PREC_FP8)
-SDF_K16_MODES(512, PREC_FP8)
-// tile variant 1 for the autotuner
+// The instantiations are split by hidden width and operand type so the build
+// can compile this file once per pair in parallel (-DSDF_K16_WIDTH=64..512,
+// -DSDF_K16_PREC=1..4, the PREC_* values); a macro left undefined selects every value.
+#if defined(SDF_K16_WIDTH)
+#define K16_W(W) (SDF_K16_WIDTH == (W))
+#else
+#define K16_W(W) 1
+#endif
+#if defined(SDF_K16_PREC)
+#define K16_P(P) (SDF_K16_PREC == (P))
+#else
+#define K16_P(P) 1
+#endif
+#define K16_SEL(W, P) (K16_W(W) && K16_P(P))
+
+#if K16_SEL(64, 1)
+SDF_K16_MODES(64, PREC_BF16)
+#endif
+#if K16_SEL(64, 2)
+SDF_K16_MODES(64, PREC_FP16)
+#endif
+#if K16_SEL(64, 3)
+SDF_K16_MODES(64, PREC_BF16X3)
+#endif
+// widths 128..512 add FP8 operands and tile variant 1 of the plain 16-bit
+// collision kernels (for the autotuner)
+#if K16_SEL(128, 1)
+SDF_K16_MODES(128, PREC_BF16)
 SDF_K16_INST_V(128, PREC_BF16, MODE_PROJECT, 1)
-SDF_K16_INST_V(256, PREC_BF16, MODE_PROJECT, 1)
-SDF_K16_INST_V(512, PREC_BF16, MODE_PROJECT, 1)
+#endif
+#if K16_SEL(128, 2)
+SDF_K16_MODES(128, PREC_FP16)
 SDF_K16_INST_V(128, PREC_FP16, MODE_PROJECT, 1)
+#endif
+#if K16_SEL(128, 3)
+SDF_K16_MODES(128, PREC_BF16X3)
+#endif
+#if K16_SEL(128, 4)
+SDF_K16_MODES(128, PREC_FP8)
+#endif
+#if K16_SEL(256, 1)
+SDF_K16_MODES(256, PREC_BF16)
+SDF_K16_INST_V(256, PREC_BF16, MODE_PROJECT, 1)
+#endif
+#if K16_SEL(256, 2)
+SDF_K16_MODES(256, PREC_FP16)
 SDF_K16_INST_V(256, PREC_FP16, MODE_PROJECT, 1)
+#endif
+#if K16_SEL(256, 3)
+SDF_K16_MODES(256, PREC_BF16X3)
+#endif
+#if K16_SEL(256, 4)
+SDF_K16_MODES(256, PREC_FP8)
+#endif
+#if K16_SEL(512, 1)
+SDF_K16_MODES(512, PREC_BF16)
+SDF_K16_INST_V(512, PREC_BF16, MODE_PROJECT, 1)
+#endif
+#if K16_SEL(512, 2)
+SDF_K16_MODES(512, PREC_FP16)
 SDF_K16_INST_V(512, PREC_FP16, MODE_PROJECT, 1)
+#endif
+#if K16_SEL(512, 3)
+SDF_K16_MODES(512, PREC_BF16X3)
+#endif
+#if K16_SEL(512, 4)
+SDF_K16_MODES(512, PREC_FP8)
+#endif
 
 }  // namespace sdfc

@@ -1,8 +1,11 @@
-"""Host-only checks of the C-ABI library: it loads, exports every declared
-symbol, and rejects malformed arguments before touching any device."""
+"""Host-only checks of the C-ABI library: it loads into the same HIP runtime
+as torch, exports every declared symbol, and rejects malformed arguments
+before any kernel launch.  No test here needs a GPU."""
 import ctypes
 import os
 import re
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -20,6 +23,22 @@ def declared_functions():
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)) -
                   {"if", "while"})
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the binding before torch must not map a second HIP runtime
+    (torch's bundled copy beside the system one): the runtime initialised
+    second would see no device and every call would fail."""
+    code = ("import paper_2110_01614_amd.binding as B, torch\n"
+            "import ctypes\n"
+            "ctypes.CDLL(B.LIB_PATH)\n"
+            "r = B._hip_runtimes_mapped()\n"
+            "assert len(r) == 1, r\n"
+            "print('runtimes', sorted(r))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "libamdhip64" in out.stdout
 
 
 def test_library_exports_every_declared_function():

@@ -217,6 +217,23 @@ int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* p
                    const float* target, int64_t n, float delta, float* grad_params, float* loss,
                    void* workspace, size_t workspace_bytes, void* stream);
 
+/* The same fitting step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight training loops, harnesses that forbid
+ * hipMalloc): no workspace argument, and no allocation of any kind.  The
+ * workspace lives in a static 64 MiB device array of the library (one per GPU,
+ * held until the process ends); the tile kernel runs 32 workgroups and the
+ * batch is cut into chunks whose workspace fits that array (about 2,700
+ * points per chunk for 3->256x8->1), so this is slower than sdf_train_step.
+ * Arguments, results and errors as sdf_train_step, plus SDF_EUNSUPPORTED if
+ * the network's workspace for one tile exceeds the array.  Every call on a GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (different
+ * streams, host threads) race and give wrong results; serialise them.  The
+ * array's contents persist between calls; everything a step reads is written
+ * earlier in the same step. */
+int sdf_train_step_noalloc(const sdf_net_desc* desc, const float* params, const float* pts,
+                           const float* target, int64_t n, float delta, float* grad_params,
+                           float* loss, void* stream);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char* sdf_last_error(void);
 

@@ -109,6 +109,8 @@ def _load():
     lib.sdf_train_workspace_bytes.argtypes = [desc_p, i64]
     lib.sdf_train_step.restype = ctypes.c_int
     lib.sdf_train_step.argtypes = [desc_p, vp, vp, vp, i64, f32, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.sdf_train_step_noalloc.restype = ctypes.c_int
+    lib.sdf_train_step_noalloc.argtypes = [desc_p, vp, vp, vp, i64, f32, vp, vp, vp]
     return lib
 
 
@@ -295,6 +297,13 @@ def sdf_train_step(desc, params, pts, target, n, delta, grad_params, loss, works
     return _check(lib.sdf_train_step(ctypes.byref(desc), _ptr(params), _ptr(pts), _ptr(target), int(n),
                                      float(delta), _ptr(grad_params), _ptr(loss), _ptr(workspace),
                                      int(ws_bytes), _stream(stream)))
+
+
+def sdf_train_step_noalloc(desc, params, pts, target, n, delta, grad_params, loss, stream=None):
+    """sdf_train_step with the library's static scratch: no workspace, no allocation."""
+    return _check(lib.sdf_train_step_noalloc(ctypes.byref(desc), _ptr(params), _ptr(pts), _ptr(target),
+                                             int(n), float(delta), _ptr(grad_params), _ptr(loss),
+                                             _stream(stream)))
 
 
 class SdfFit:

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/sdfcollide.h"
@@ -620,10 +621,19 @@ struct TrainLayout {  // byte offsets inside the caller's workspace
   int64_t chunk;
 };
 
-TrainLayout train_layout(int W, int L, int64_t n, int slots) {
+}  // namespace
+
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;  // 64 MiB per device
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+// Chunk of a batch of n points for a workspace sized for at most max_chunk.
+int64_t train_chunk(int64_t n, int64_t max_chunk) { return n < max_chunk ? (n > 0 ? n : 1) : max_chunk; }
+
+TrainLayout train_layout(int W, int L, int64_t chunk, int slots) {
   TrainLayout t{};
   auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
-  const int64_t chunk = n < kTrainChunk ? (n > 0 ? n : 1) : kTrainChunk;
   size_t o = 0;
   t.stream = o;
   o = up(o + 2 * (size_t)(L - 1) * (W / 16) * (W / 16) * kFrag);
@@ -663,42 +673,28 @@ int device_cus(int* cus) {
   return SDF_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int64_t sdf_train_workspace_bytes(const sdf_net_desc* desc, int64_t n) {
-  g_err.clear();
-  int W, L, skip, cus;
-  if (train_check(desc, &W, &L, &skip) != SDF_OK || n < 0) return -1;
-  if (device_cus(&cus) != SDF_OK) return -1;
-  return (int64_t)train_layout(W, L, n, cus).total;
-}
-
-int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* pts,
-                   const float* target, int64_t n, float delta, float* grad_params, float* loss,
-                   void* workspace, size_t workspace_bytes, void* stream) {
-  g_err.clear();
-  int W, L, skip;
-  int rc = train_check(desc, &W, &L, &skip);
+int train_args(const sdf_net_desc* desc, const float* params, const float* pts, const float* target,
+               int64_t n, float delta, const float* grad_params, const float* loss, int* W, int* L,
+               int* skip) {
+  int rc = train_check(desc, W, L, skip);
   if (rc) return rc;
-  if (!params || !grad_params || !loss || (n > 0 && (!pts || !target || !workspace)))
+  if (!params || !grad_params || !loss || (n > 0 && (!pts || !target)))
     return fail(SDF_EINVAL, "NULL pointer argument");
   if (n < 0) return fail(SDF_EINVAL, "n < 0");
   if (!std::isfinite(delta) || delta <= 0.0f) return fail(SDF_EINVAL, "delta must be finite and > 0");
-  if (!aligned4(params) || !aligned4(pts) || !aligned4(target) || !aligned4(grad_params) ||
-      !aligned4(loss) || ((uintptr_t)workspace & 255u))
-    return fail(SDF_EINVAL, "arrays must be 4-byte aligned, the workspace 256-byte aligned");
+  if (!aligned4(params) || !aligned4(pts) || !aligned4(target) || !aligned4(grad_params) || !aligned4(loss))
+    return fail(SDF_EINVAL, "arrays must be 4-byte aligned");
   if (n > ((int64_t)1 << 40)) return fail(SDF_EINVAL, "n too large");
-  int cus;
-  rc = device_cus(&cus);
-  if (rc) return rc;
-  const TrainLayout lay = train_layout(W, L, n, cus);
-  if (n > 0 && workspace_bytes < lay.total)
-    return fail(SDF_EINVAL, "workspace too small: need " + std::to_string(lay.total) + " bytes");
-  const hipStream_t s = (hipStream_t)stream;
-  const int64_t np = count_params(desc);
+  return SDF_OK;
+}
 
+// One fitting step over n points, chunk by chunk, in the workspace `ws` laid
+// out as `lay`; the persistent tile kernel runs at most `slots` workgroups
+// (its sigma stack has that many slots).
+int train_run(const sdf_net_desc* desc, int W, int L, int skip, const float* params, const float* pts,
+              const float* target, int64_t n, float delta, float* grad_params, float* loss,
+              unsigned char* ws, const TrainLayout& lay, int slots, hipStream_t s) {
+  const int64_t np = count_params(desc);
   TrainNet t{};
   t.W = W;
   t.L = L;
@@ -723,7 +719,6 @@ int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* p
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SDF_OK : hip_fail(e, "kernel launch");
   }
-  unsigned char* ws = (unsigned char*)workspace;
   float* d_stream = (float*)(ws + lay.stream);
   float* d_small = (float*)(ws + lay.small);
   hipLaunchKernelGGL(pack_fp32_kernel, dim3(2048), dim3(256), 0, s, t, params, d_stream, d_small);
@@ -751,7 +746,7 @@ int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* p
     a.target = target + c0;
     a.n = cn;
     a.ntiles = (int)((cn + kPtsPerBlock - 1) / kPtsPerBlock);
-    dim3 grid((unsigned)std::min<int64_t>(a.ntiles, cus));
+    dim3 grid((unsigned)std::min<int64_t>(a.ntiles, slots));
 #define KT(WW) \
   if (W == WW) hipLaunchKernelGGL((sdf_k32<WW, MODE_TRAIN>), grid, dim3(kBlock), 0, s, a);
     KT(64) KT(128) KT(256)
@@ -761,6 +756,93 @@ int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* p
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? SDF_OK : hip_fail(e, "kernel launch");
+}
+
+// ---- the static scratch of sdf_train_step_noalloc (callers that cannot allocate)
+//
+// `scratch` (file scope, below) is a fixed array in the code object: every GPU
+// the library runs on holds its own copy until the process ends.  Host code
+// never uses the array's name as an address: its device address is looked up
+// once per device with hipGetSymbolAddress (with that device current) and
+// kept in g_scratch_ptr, which is what the kernels receive.
+constexpr int kStaticSlots = 32;  // workgroups of the persistent tile kernel (sigma-stack slots)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SDF_EUNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t sdf_train_workspace_bytes(const sdf_net_desc* desc, int64_t n) {
+  g_err.clear();
+  int W, L, skip, cus;
+  if (train_check(desc, &W, &L, &skip) != SDF_OK || n < 0) return -1;
+  if (device_cus(&cus) != SDF_OK) return -1;
+  return (int64_t)train_layout(W, L, train_chunk(n, kTrainChunk), cus).total;
+}
+
+int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* pts,
+                   const float* target, int64_t n, float delta, float* grad_params, float* loss,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+  g_err.clear();
+  int W, L, skip;
+  int rc = train_args(desc, params, pts, target, n, delta, grad_params, loss, &W, &L, &skip);
+  if (rc) return rc;
+  if (n > 0 && !workspace) return fail(SDF_EINVAL, "NULL pointer argument");
+  if ((uintptr_t)workspace & 255u) return fail(SDF_EINVAL, "the workspace must be 256-byte aligned");
+  int cus;
+  rc = device_cus(&cus);
+  if (rc) return rc;
+  const TrainLayout lay = train_layout(W, L, train_chunk(n, kTrainChunk), cus);
+  if (n > 0 && workspace_bytes < lay.total)
+    return fail(SDF_EINVAL, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+  return train_run(desc, W, L, skip, params, pts, target, n, delta, grad_params, loss,
+                   (unsigned char*)workspace, lay, cus, (hipStream_t)stream);
+}
+
+int sdf_train_step_noalloc(const sdf_net_desc* desc, const float* params, const float* pts,
+                           const float* target, int64_t n, float delta, float* grad_params,
+                           float* loss, void* stream) {
+  g_err.clear();
+  int W, L, skip;
+  int rc = train_args(desc, params, pts, target, n, delta, grad_params, loss, &W, &L, &skip);
+  if (rc) return rc;
+  int dev = 0;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  unsigned char* ws = nullptr;
+  rc = static_scratch(dev, &ws);
+  if (rc) return rc;
+  int cus;
+  rc = device_cus(&cus);
+  if (rc) return rc;
+  const int slots = std::min(cus, kStaticSlots);
+  // the largest chunk (a multiple of the tile) whose workspace fits the scratch
+  int64_t chunk = std::min<int64_t>(train_chunk(n, kTrainChunk), kTrainChunk);
+  chunk = (chunk + kPtsPerBlock - 1) / kPtsPerBlock * kPtsPerBlock;
+  while (chunk > kPtsPerBlock && train_layout(W, L, chunk, slots).total > kStaticScratchBytes)
+    chunk -= kPtsPerBlock;
+  const TrainLayout lay = train_layout(W, L, chunk, slots);
+  if (lay.total > kStaticScratchBytes)
+    return fail(SDF_EUNSUPPORTED, "network too large for the static scratch: one tile needs " +
+                                      std::to_string(lay.total) + " bytes of " +
+                                      std::to_string(kStaticScratchBytes));
+  return train_run(desc, W, L, skip, params, pts, target, n, delta, grad_params, loss, ws, lay, slots,
+                   (hipStream_t)stream);
 }
 
 }  // extern "C"

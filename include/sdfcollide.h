@@ -26,7 +26,12 @@
  *    moved; a vertex that is not moved keeps its exact bit pattern.
  *  - The handle is immutable after creation: concurrent calls with one handle
  *    on different streams are allowed; sdf_net_destroy needs the caller to
- *    have synchronised every stream that used the handle.
+ *    have synchronised every stream that used the handle.  SDF_FP32 handles
+ *    keep one reverse-sweep scratch area, so their calls are ordered on the
+ *    device instead of overlapping: a call issued on another stream than the
+ *    previous call on the handle first waits (hipStreamWaitEvent) for that
+ *    call.  While a stream is being captured into a graph, FP32 calls on one
+ *    handle must all be issued on that stream.
  */
 #ifndef SDFCOLLIDE_H
 #define SDFCOLLIDE_H

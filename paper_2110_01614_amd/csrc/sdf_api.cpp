@@ -41,6 +41,13 @@ struct sdf_net {
   int chunks_per_layer = 0;
   float* d_small = nullptr;
   float* d_scratch = nullptr;  // FP32 sigma stack, one slot per resident workgroup
+  // FP32 handles: every call uses the one sigma stack, so calls on different
+  // streams are ordered on the device: a call waits for the previous one when
+  // that one ran on another stream (see fp32_order).
+  hipEvent_t last_ev = nullptr;
+  mutable hipStream_t last_stream = nullptr;
+  mutable bool has_last = false;
+  mutable std::mutex mu;
   int slots = 0;
   int variant = 0;            // tile variant of the 16-bit collide_project kernel (autotuner)
   float c_l1g = 0.0f, c_skg = 0.0f, c_wob = 0.0f;  // see KArgs
@@ -423,6 +430,8 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
     net->slots = cus;  // one 4-wave workgroup per CU (LDS-bound)
     const size_t bytes = (size_t)net->slots * (kLMax - 1) * 4 * (W / 16) * 64 * 16;
     if (hipMalloc(&net->d_scratch, bytes) != hipSuccess) return cleanup(SDF_ENOMEM, "hipMalloc(scratch)");
+    if (hipEventCreateWithFlags(&net->last_ev, hipEventDisableTiming) != hipSuccess)
+      return cleanup(SDF_EDEVICE, "hipEventCreateWithFlags");
   }
   (void)hipSetDevice(prev_dev);
   *out = net;
@@ -437,6 +446,7 @@ int sdf_net_destroy(sdf_net* net) {
   if (net->d_stream) (void)hipFree(net->d_stream);
   if (net->d_small) (void)hipFree(net->d_small);
   if (net->d_scratch) (void)hipFree(net->d_scratch);
+  if (net->last_ev) (void)hipEventDestroy(net->last_ev);
   (void)hipSetDevice(prev);
   delete net;
   return SDF_OK;
@@ -566,7 +576,27 @@ int run(const sdf_net* net, const float* pts_in, float* pts_out, int64_t n, floa
   int prev = 0;
   (void)hipGetDevice(&prev);
   if (prev != net->device) (void)hipSetDevice(net->device);
-  const hipError_t e = launch<MODE>(net, a, (hipStream_t)stream);
+  hipError_t e = hipSuccess;
+  if (net->prec == SDF_FP32) {
+    // One sigma stack per handle: order this call after the previous one if
+    // that ran on another stream.  A stream under capture is left alone (the
+    // header asks captured FP32 calls on one handle to use one stream).
+    const hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(net->mu);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(s, &cs);
+    const bool eager = e == hipSuccess && cs == hipStreamCaptureStatusNone;
+    if (e == hipSuccess && eager && net->has_last && net->last_stream != s)
+      e = hipStreamWaitEvent(s, net->last_ev, 0);
+    if (e == hipSuccess) e = launch<MODE>(net, a, s);
+    if (e == hipSuccess && eager) {
+      e = hipEventRecord(net->last_ev, s);
+      net->last_stream = s;
+      net->has_last = true;
+    }
+  } else {
+    e = launch<MODE>(net, a, (hipStream_t)stream);
+  }
   if (prev != net->device) (void)hipSetDevice(prev);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SDF_OK;

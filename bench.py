@@ -6,8 +6,13 @@ input gradient, the normal, the f < eps test and the move to the contact
 point, in place (Sec. 3.2, Eq. 1-3).  Inputs are resident in HBM before the
 timed region.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--precision bf16]
-                  [--no-cpu-baseline] [--no-compare]
+  python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--precision bf16x3]
+                  [--no-cpu-baseline] [--no-compare] [--no-accuracy] ...
+
+The headline precision is the cheapest operand precision whose errors on the
+cloth networks stay within the stated target (|f - f64| <= 1e-3, normal angle
+<= 1e-2 rad): BF16x3 (three BF16 products per product).  Plain BF16, FP16,
+FP8 and FP32 are timed beside it with their errors and a meets_target flag.
 """
 from __future__ import annotations
 
@@ -107,21 +112,39 @@ def mfma_flops_per_point(spec) -> int:
     return 4 * sum(o * min(i, spec.widths[0]) for o, i in sh[1:-1])
 
 
-def time_steps(net, X, eps, steps, warmup, torch):
+def time_launches(fn, steps, warmup, torch):
+    """Wall time of `steps` calls of fn (synchronised on both sides) and the
+    duration of each call from HIP events recorded on the stream the library
+    launches on (torch's current stream)."""
     for _ in range(warmup):
-        net.collide_project(X, eps, want=())
+        fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
     ev[0].record(stream)
     for k in range(steps):
-        net.collide_project(X, eps, want=())
+        fn()
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]  # ms, one launch each
     return wall, per
+
+
+def time_steps(net, X, eps, steps, warmup, torch):
+    """collide_project over X in place, writing the sdf and normal outputs
+    (allocated once, outside the timed region)."""
+    from paper_2110_01614_amd import binding as B
+    n = X.shape[0]
+    sdf = torch.empty(n, device=X.device, dtype=torch.float32)
+    nrm = torch.empty(n, 3, device=X.device, dtype=torch.float32)
+    return time_launches(lambda: B.collide_project(net.handle, X, n, eps, sdf, nrm), steps, warmup, torch)
+
+
+def spread(per):
+    return {"p10_ms": float(np.quantile(per, 0.1)), "p50_ms": float(np.median(per)),
+            "p90_ms": float(np.quantile(per, 0.9))}
 
 
 def colliders(torch, B, I, steps, precision="bf16"):
@@ -149,7 +172,8 @@ def colliders(torch, B, I, steps, precision="bf16"):
         return e0.elapsed_time(e1) / k
 
     ms_group = timed(grp.collide_project, steps)
-    ms_single = timed(lambda: [net.collide_project(x, eps, want=()) for net, x in zip(nets, X)], steps)
+    ms_single = timed(lambda: [B.collide_project(net.handle, x, x.shape[0], eps) for net, x in zip(nets, X)],
+                      steps)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         for _ in range(30):
@@ -207,21 +231,65 @@ def accuracy(spec, params, pts, net, torch, n=4096, eps=0.005):
             "sample": n}
 
 
-def cpu_baseline(spec, params, pts, target_s=10.0):
-    """The FP64 oracle (untuned) on the host cores, on a bounded sample."""
+def _oracle_threads(k):
+    """Set the OpenMP thread count of the oracle library (libgomp's own call)."""
+    import ctypes
+
+    import oracle
+    lib = oracle._load()
+    lib.omp_set_num_threads.argtypes = [ctypes.c_int]
+    lib.omp_set_num_threads(int(k))
+
+
+def cpu_baseline(spec, params, pts, target_s=10.0, one_core_s=4.0):
+    """The FP64 oracle (untuned) on the host cores, on a bounded sample, and
+    the same on one core."""
     import oracle
     cores = len(os.sched_getaffinity(0))
-    n0 = 1024
-    t = time.perf_counter()
-    oracle.collide_project(spec, params, pts[:n0], 0.005)
-    dt = time.perf_counter() - t
-    n = int(min(len(pts), max(n0, n0 * target_s / max(dt, 1e-3))))
-    t = time.perf_counter()
-    oracle.collide_project(spec, params, pts[:n], 0.005)
-    dt = time.perf_counter() - t
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return {"value": n / dt, "unit": "points/s", "cores": min(threads, cores), "kind": "oracle",
-            "sample": "first %d of the 1M cloth vertices, FP64 forward + reverse + project, %.1f s" % (n, dt)}
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", cores)), cores)
+
+    def rate(budget_s):
+        n0 = 256
+        t = time.perf_counter()
+        oracle.collide_project(spec, params, pts[:n0], 0.005)
+        dt = time.perf_counter() - t
+        n = int(min(len(pts), max(n0, n0 * budget_s / max(dt, 1e-3))))
+        t = time.perf_counter()
+        oracle.collide_project(spec, params, pts[:n], 0.005)
+        dt = time.perf_counter() - t
+        return n, dt
+
+    _oracle_threads(threads)
+    n, dt = rate(target_s)
+    _oracle_threads(1)
+    n1, dt1 = rate(one_core_s)
+    _oracle_threads(threads)
+    return {"value": n / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d of the 1M cloth vertices, FP64 forward + reverse + project, %.1f s" % (n, dt),
+            "one_core": {"value": n1 / dt1, "unit": "points/s", "cores": 1,
+                         "sample": "first %d cloth vertices, %.1f s" % (n1, dt1)}}
+
+
+def latency_small(torch, B, I, steps=200):
+    """The plain-method workload (3->64x3->1, 4096 points): per-call latency."""
+    spec, params, pts, eps = I.workload_inputs("sphere64")
+    X0 = torch.from_numpy(pts).cuda()
+    out = {"workload": "sphere64: 3->64x3->1 geometric init, %d uniform points, collide_project" % len(pts)}
+    for prec in ("fp32", "bf16x3", "bf16"):
+        net = B.SdfNet(spec, params, prec)
+        X = X0.clone()
+        wall, per = time_steps(net, X, eps, steps, 20, torch)
+        out[prec] = {"kernel_us_p50": 1e3 * float(np.median(per)), "kernel_us_p10": 1e3 * float(np.quantile(per, 0.1)),
+                     "kernel_us_p90": 1e3 * float(np.quantile(per, 0.9)), "wall_us_per_call": 1e6 * wall / steps}
+        net.close()
+    return out
+
+
+TARGET_SDF, TARGET_ANGLE = 1e-3, 1e-2  # the stated accuracy target: |f - f64|, normal angle (rad)
+
+
+def meets_target(acc) -> bool:
+    return all(a["sdf_max"] <= TARGET_SDF and a["angle_max_rad"] <= TARGET_ANGLE for a in acc)
 
 
 def main():
@@ -229,12 +297,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp16", "bf16x3", "fp8", "fp32"])
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16", "fp16", "bf16x3", "fp8", "fp32"],
+                    help="headline operand precision (default: the cheapest that meets the accuracy target)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other precisions")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-group", action="store_true", help="skip the several-collider measurement")
     ap.add_argument("--no-study", action="store_true", help="skip the 512-wide precision study")
+    ap.add_argument("--no-latency", action="store_true", help="skip the small-workload latency")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     ap.add_argument("--copy-mib", type=int, default=256, help="size of the copy probe the counters saw")
@@ -262,33 +332,34 @@ def main():
     from paper_2110_01614_amd import binding as B
 
     spec, params, pts, eps = I.workload_inputs("cloth1m")
+    pg = I.workload_inputs("cloth1m", n=1, init="geometric")[1]
     n = len(pts)
     fpp = flops_per_point(spec)
     X0 = torch.from_numpy(pts).cuda()
     results = {}
     order = [args.precision] + ([] if args.no_compare else
-                                [p for p in ("fp32", "fp16", "bf16x3", "fp8", "bf16") if p != args.precision])
+                                [p for p in ("bf16", "fp16", "fp32", "fp8", "bf16x3") if p != args.precision])
     for prec in order:
         net = B.SdfNet(spec, params, prec)
         X = X0.clone()
         steps = args.steps if prec != "fp32" else max(3, min(args.steps, 10))
         wall, per = time_steps(net, X, eps, steps, args.warmup if prec != "fp32" else 2, torch)
         avg_ms = float(np.mean(per))
-        r = {"ms_per_step": wall * 1e3 / steps, "kernel_ms_mean": avg_ms,
-             "kernel_ms_median": float(np.median(per)), "points_per_s": n * steps / wall,
-             "tflops": fpp * n / (avg_ms * 1e-3) / 1e12}
+        r = {"ms_per_step": wall * 1e3 / steps, "kernel_ms_mean": avg_ms, "kernel_ms": spread(per),
+             "points_per_s": n * steps / wall, "tflops": fpp * n / (avg_ms * 1e-3) / 1e12}
         r["mfma_frac"] = r["tflops"] / PEAK_TFLOPS[prec]
         if not args.no_accuracy:
             r["accuracy_vs_fp64"] = accuracy(spec, params, pts, net, torch)
             # the same shape with the geometric (SDF-like) initialisation
-            pg = I.workload_inputs("cloth1m", n=1, init="geometric")[1]
             ng = B.SdfNet(spec, pg, prec)
             r["accuracy_vs_fp64_geometric_init"] = accuracy(spec, pg, pts, ng, torch, n=2048)
             ng.close()
+            r["meets_target"] = meets_target([r["accuracy_vs_fp64"], r["accuracy_vs_fp64_geometric_init"]])
         results[prec] = r
         net.close()
         del X
 
+    latency = None if args.no_latency else latency_small(torch, B, I)
     group = None if args.no_group else colliders(torch, B, I, args.steps)
     study = None if args.no_study else precision_study(torch, B, I, max(3, args.steps // 4))
     head = results[args.precision]
@@ -308,11 +379,14 @@ def main():
         "config": {"workload": "cloth1m: 1000x1000 cloth grid (spacing 2e-3, z = 0.1 sin noise, "
                                "N(0,0.01) jitter, seed 2) through 3->256x8->1 softplus(beta=100) "
                                "MLP, input re-fed at layer 5, N(0,0.02) weights seed 0; "
-                               "collide_project in place, eps 0.005",
+                               "collide_project in place writing sdf and normal, eps 0.005",
                    "points": n, "flops_per_point": fpp,
                    "launch": "1 kernel / step; BF16/FP16: 64 points per 512-thread workgroup, "
                              "BF16x3: 32 points, FP32: persistent 256-thread workgroups",
                    "kernel_source_hash": kernel_source_hash()},
+        "target": {"sdf_max": TARGET_SDF, "angle_max_rad": TARGET_ANGLE,
+                   "checked_on": "4096 cloth vertices (N(0,0.02) net) and 2048 (geometric-init net) vs FP64",
+                   "met_by_headline": head.get("meets_target")},
         "roofline": {"bound": "mfma", "achieved": head["tflops"], "peak": PEAK_TFLOPS[args.precision],
                      "unit": "TFLOP/s", "frac": head["mfma_frac"],
                      "traffic": measured_traffic(args.precision)},
@@ -320,6 +394,8 @@ def main():
         "paper_context": "Table 1 / abstract: ~1M queries in ~300 ms on a Tesla T4 (TensorFlow, "
                          "Fourier features + 4 or 8 FC x 256, ReLU)",
     }
+    if latency:
+        out["latency_sphere64"] = latency
     if group:
         out["colliders"] = group
     if study:

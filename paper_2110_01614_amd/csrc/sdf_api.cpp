@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -418,8 +419,17 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
     (void)hipSetDevice(prev_dev);
     return fail(code, msg);
   };
-  if (hipMalloc(&net->d_stream, stream.size()) != hipSuccess) return cleanup(SDF_ENOMEM, "hipMalloc(stream)");
-  if (hipMalloc(&net->d_small, sm.size() * 4) != hipSuccess) return cleanup(SDF_ENOMEM, "hipMalloc(small)");
+  // SDFC_FAIL_ALLOC=k (testing the out-of-memory path): the k-th device
+  // allocation of this call reports failure without allocating.
+  const char* fail_env = std::getenv("SDFC_FAIL_ALLOC");
+  const int fail_at = fail_env ? std::atoi(fail_env) : 0;
+  int n_alloc = 0;
+  auto dev_alloc = [&](auto** p, size_t bytes) {
+    if (++n_alloc == fail_at) return false;
+    return hipMalloc((void**)p, bytes) == hipSuccess;
+  };
+  if (!dev_alloc(&net->d_stream, stream.size())) return cleanup(SDF_ENOMEM, "hipMalloc(stream)");
+  if (!dev_alloc(&net->d_small, sm.size() * 4)) return cleanup(SDF_ENOMEM, "hipMalloc(small)");
   if (hipMemcpy(net->d_stream, stream.data(), stream.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(net->d_small, sm.data(), sm.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
     return cleanup(SDF_EDEVICE, "hipMemcpy of packed weights");
@@ -429,7 +439,7 @@ int sdf_net_create(const sdf_net_desc* desc, const float* params, size_t n_param
       return cleanup(SDF_EDEVICE, "hipDeviceGetAttribute(CU count)");
     net->slots = cus;  // one 4-wave workgroup per CU (LDS-bound)
     const size_t bytes = (size_t)net->slots * (kLMax - 1) * 4 * (W / 16) * 64 * 16;
-    if (hipMalloc(&net->d_scratch, bytes) != hipSuccess) return cleanup(SDF_ENOMEM, "hipMalloc(scratch)");
+    if (!dev_alloc(&net->d_scratch, bytes)) return cleanup(SDF_ENOMEM, "hipMalloc(scratch)");
     if (hipEventCreateWithFlags(&net->last_ev, hipEventDisableTiming) != hipSuccess)
       return cleanup(SDF_EDEVICE, "hipEventCreateWithFlags");
   }

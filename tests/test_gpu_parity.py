@@ -7,10 +7,11 @@ Tolerances:
   says so; the measured statistics are always printed.
   FP8 (E4M3) operands, no target is stated; the bound comes from the
   arithmetic: 3 mantissa bits (unit roundoff 2^-4) on both operands of every
-  hidden contraction.  A numpy model of exactly these roundings gives, on
-  well-conditioned (geometric-init) nets of widths 256-512, |f - f64| <= 0.075
-  and normal angles with p99 <= 0.08 and max <= 0.27 rad; the tests assert
-  |f - f64| <= 0.15, p99 angle <= 0.15 and max angle <= 0.6 rad there.
+  hidden contraction.  The operand-rounding model of tests/precision_model.py
+  gives, on geometric-init nets of widths 256 and 512 (2048 uniform points),
+  |f - f64| <= 0.089 and normal angles with p99 <= 0.103 and max <= 0.153 rad
+  (tests/test_precision_model.py::test_fp8_error_bound_of_the_gpu_tests); the
+  tests assert |f - f64| <= 0.15, p99 angle <= 0.15 and max angle <= 0.6 rad.
 Hits are decided in FP32 on both sides of the comparison that must be exact:
 the GPU's flag equals (its own f < eps); against FP64 the flags agree wherever
 |f64 - eps| exceeds the SDF tolerance.
@@ -408,3 +409,61 @@ def test_fp32_handle_on_two_streams_is_ordered():
         assert np.all(np.abs(f - f64) <= 1e-5 * (1 + np.abs(f64)))
         assert angle(g, g64).max() <= 1e-4
     net.close()
+
+
+# The stated accuracy target on the cloth workload's two networks: met or
+# missed per precision exactly as the operand-rounding model predicts
+# (tests/test_precision_model.py): plain BF16 misses it on both, FP16 misses
+# the angle bar on the N(0, 0.02) net and meets both bars on the geometric
+# one, BF16x3 meets both on both.
+TARGET_CASES = [("bf16", "normal", False), ("bf16", "geometric", False), ("fp16", "normal", False),
+                ("fp16", "geometric", True), ("bf16x3", "normal", True), ("bf16x3", "geometric", True)]
+
+
+@pytest.mark.parametrize("precision,init,meets", TARGET_CASES)
+def test_accuracy_target_on_the_cloth_networks(precision, init, meets):
+    """Max |f - f64| <= 1e-3 and max normal angle <= 1e-2 rad over 4096 cloth
+    vertices, through query_grad."""
+    spec, params, pts, eps = I.workload_inputs("cloth1m", init=init)
+    P = np.ascontiguousarray(pts[np.random.default_rng(3).choice(len(pts), 4096, replace=False)])
+    f64, g64 = oracle.mlp_eval(spec, params, P)
+    net = B.SdfNet(spec, params, precision)
+    f, g = net.query_grad(torch.from_numpy(P).cuda())
+    torch.cuda.synchronize()
+    f, g = f.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+    net.close()
+    ferr, ang = np.abs(f - f64).max(), angle(g, g64).max()
+    record("accuracy_target", precision=precision, init=init, sdf_max=float(ferr), ang_max=float(ang))
+    within = ferr <= 1e-3 and ang <= 1e-2
+    assert within == meets, (precision, init, ferr, ang)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "bf16x3"])
+def test_zero_gradient_hit_is_not_moved(precision):
+    """A network whose output weights are zero: f = b_o < eps everywhere and
+    grad f = 0 exactly, so every vertex is a hit, its normal is 0 and it is
+    not moved (bits kept)."""
+    spec = I.NetSpec((128,) * 4, 2)
+    params = np.zeros(I.param_count(spec), np.float32)
+    params[-1] = -0.1
+    pts = I.uniform_points(777, 40)
+    got = run_gpu(spec, params, pts, precision, 0.005)
+    assert np.all(got["hit"] == 1)
+    assert np.all(got["sdf"] == np.float32(-0.1))
+    assert np.all(got["grad"] == 0.0) and np.all(got["normal"] == 0.0)
+    assert np.array_equal(got["pts"].view(np.uint32), pts.view(np.uint32))
+
+
+@pytest.mark.parametrize("nth", [1, 2, 3])
+def test_device_allocation_failure_is_reported(nth, monkeypatch):
+    """SDFC_FAIL_ALLOC=k makes the k-th device allocation of sdf_net_create
+    fail: the call returns SDF_ENOMEM and leaves nothing behind."""
+    spec, params, pts, eps = I.workload_inputs("sphere64", n=64)
+    d = B.make_desc(spec.widths, spec.skip, precision="fp32")
+    monkeypatch.setenv("SDFC_FAIL_ALLOC", str(nth))
+    with pytest.raises(B.SdfError) as e:
+        B.sdf_net_create(d, params)
+    assert e.value.code == B.SDF_ENOMEM
+    monkeypatch.delenv("SDFC_FAIL_ALLOC")
+    h = B.sdf_net_create(d, params)
+    B.sdf_net_destroy(h)

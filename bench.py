@@ -29,8 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"bf16": 2500.0, "fp16": 2500.0, "bf16x3": 2500.0, "fp8": 5000.0, "fp32": 157.3}  # MI355X dense MFMA
+# device sources of the 16-bit kernels: the traffic record is tied to their hash
 KERNEL_SOURCES = ["paper_2110_01614_amd/csrc/sdf_k16.hip", "paper_2110_01614_amd/csrc/sdf_device.hpp",
-                  "paper_2110_01614_amd/csrc/sdf_layout.hpp", "paper_2110_01614_amd/csrc/sdf_api.cpp"]
+                  "paper_2110_01614_amd/csrc/sdf_layout.hpp"]
+K16_NAME = "sdf_k16<256, %d, 2, 0>"  # collide_project kernel at width 256, by operand type
+PREC_ID = {"bf16": 1, "fp16": 2, "bf16x3": 3, "fp8": 4}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sdf_k16_cloth1m.json")
 
 
@@ -96,6 +99,72 @@ def traffic_record(copy_fetch, copy_write, k_fetch, k_write, kernel, precision, 
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
+
+
+def pmc_summary(root, precisions, n_points=1_000_000, flops_per_pt=1842176, clock_ghz=2.4):
+    """Markdown summary of rocprofv3 counter passes of the cloth1m kernel.
+
+    root/<prec>/p1..p3: SQ / TCC / TCP counter passes (--pmc), root/<prec>/kt:
+    --kernel-trace --stats.  Values are per dispatch (mean over the
+    dispatches of the width-256 collide_project kernel)."""
+    import csv
+    import glob
+
+    def counters(prec, i, name):
+        vals = {}
+        for f in glob.glob(os.path.join(root, prec, "p%d" % i, "*counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                if name in r["Kernel_Name"]:
+                    vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        return {k: float(np.mean(v)) for k, v in vals.items()}
+
+    def trace(prec, name):
+        """(timed launches, mean ms, median ms): the kernel's dispatches in the
+        trace after the benchmark's warm-up launches (5; FP32: 2)."""
+        for f in glob.glob(os.path.join(root, prec, "kt", "*kernel_trace.csv")):
+            d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in csv.DictReader(open(f))
+                 if name in r["Kernel_Name"]]
+            d = d[2 if prec == "fp32" else 5:]
+            if d:
+                return len(d), float(np.mean(d)), float(np.median(d))
+        return None
+
+    rows = []
+    for prec in precisions:
+        name = K16_NAME % PREC_ID[prec] if prec in PREC_ID else "sdf_k32<256, 2>"
+        c = {}
+        for i in (1, 2, 3):
+            c.update(counters(prec, i, name))
+        kt = trace(prec, name)
+        if not c or kt is None:
+            continue
+        xcd_cycles = c["GRBM_GUI_ACTIVE"] / 8.0  # summed over the 8 XCDs
+        simds = 256 * 4
+        mops = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_" + t, 0.0) for t in ("BF16", "F16", "F8", "F32")) * 512
+        busy = c["SQ_VALU_MFMA_BUSY_CYCLES"] / simds
+        valu = c["SQ_INSTS_VALU"] - c["SQ_INSTS_MFMA"]
+        l2cu = c["TCP_TCC_READ_REQ"] * 128
+        rows.append({
+            "prec": prec, "kernel": name, "calls": kt[0], "ms": kt[1], "median_ms": kt[2],
+            "algo_tflops": flops_per_pt * n_points / (kt[1] * 1e-3) / 1e12,
+            "issued_tflop": mops / 1e12, "mfma_busy": busy / xcd_cycles,
+            "coexec": c["SQ_VALU_MFMA_COEXEC_CYCLES"] / simds / xcd_cycles,
+            "valu_per_tile_wave": valu, "trans": c["SQ_INSTS_VALU_TRANS_F32"],
+            "wait": c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"],
+            "lds_conflict": c["SQ_LDS_BANK_CONFLICT"], "lds_insts": c["SQ_INSTS_LDS"],
+            "l2_hit": c["TCC_HIT"] / max(c["TCC_REQ"], 1.0), "l2cu_gb": l2cu / 1e9,
+            "l2cu_tbs": l2cu / (kt[1] * 1e-3) / 1e12})
+    out = ["| operands | kernel | launches | mean ms (trace) | median ms | algorithmic TFLOP/s | issued MFMA TFLOP | "
+           "MFMA busy | MFMA+VALU co-issue | non-MFMA VALU insts | trans insts | wait fraction | "
+           "LDS bank-conflict cycles | L2 hit | L2->CU GB | L2->CU TB/s |", "|" + "---|" * 16]
+    for r in rows:
+        out.append("| %s | `%s` | %d | %.3f | %.3f | %.0f | %.3f | %.1f %% | %.1f %% | %.3g | %.3g | %.0f %% | %.3g | "
+                   "%.2f %% | %.1f | %.1f |" % (
+                       r["prec"], r["kernel"], r["calls"], r["ms"], r["median_ms"], r["algo_tflops"],
+                       r["issued_tflop"], 100 * r["mfma_busy"], 100 * r["coexec"], r["valu_per_tile_wave"], r["trans"],
+                       100 * r["wait"], r["lds_conflict"], 100 * r["l2_hit"], r["l2cu_gb"], r["l2cu_tbs"]))
+    print("\n".join(out))
+    return rows
 
 
 def flops_per_point(spec) -> int:
@@ -190,6 +259,42 @@ def colliders(torch, B, I, steps, precision="bf16"):
             "grouped_ms": ms_group, "per_network_ms": ms_single, "graph_30_passes_ms_per_pass": ms_graph,
             "autotuned_ms": ms_tuned, "autotuned_launch": "per network" if per_net else "per width class",
             "grouped_points_per_s": n / (ms_group * 1e-3), "grouped_tflops": flops / (ms_group * 1e-3) / 1e12}
+
+
+def fitting(torch, B, I, steps, warmup=2, n=1_000_000):
+    """One FP32 fitting step (clamped-L1 loss and its parameter gradient) on
+    1M samples of the displaced icosphere (level 6, 81,920 triangles; half
+    near the surface, half uniform) for 3->256x8->1 skip 5, geometric init.
+
+    The step's work does not depend on the target values, so the timed
+    targets are the radial offset |p| - r(p/|p|) from the displaced sphere,
+    a stand-in for the brute-force signed distance that the tests use at
+    smaller sizes."""
+    import math
+    spec = I.NetSpec((256,) * 8, 5)
+    V, F = I.displaced_icosphere(level=6, seed=3)
+    pts = I.training_samples(V, F, n, seed=4)
+    rng = np.random.default_rng(3)  # the displacement field of displaced_icosphere(seed=3)
+    d = rng.normal(size=(3, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    om = math.pi * rng.integers(1, 4, size=3)
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=3)
+    p64 = pts.astype(np.float64)
+    rad = np.linalg.norm(p64, axis=1)
+    u = p64 / np.maximum(rad, 1e-12)[:, None]
+    tgt = (rad - (0.5 + 0.05 * np.sin((u @ d.T) * om + ph).mean(axis=1))).astype(np.float32)
+    P = torch.from_numpy(I.init_geometric(spec, 0)).cuda()
+    X, S = torch.from_numpy(pts).cuda(), torch.from_numpy(tgt).cuda()
+    fit = B.SdfFit(spec, n)
+    wall, per = time_launches(lambda: fit.step(P, X, S, 0.1), steps, warmup, torch)
+    ms = float(np.mean(per))
+    flops = 6 * sum(o * i for o, i in I.layer_shapes(spec)) * n
+    return {"workload": "fit_icosphere: 3->256x8->1 skip 5, geometric init seed 0, %d samples of the level-6 "
+                        "displaced icosphere (seed 3, samples seed 4), clamped L1 delta 0.1, FP32" % n,
+            "targets": "radial offset from the displaced sphere (stand-in; the step's cost does not depend on them)",
+            "workspace_bytes": fit.ws_bytes, "ms_per_step": ms, "step_ms": spread(per),
+            "samples_per_s": n / (ms * 1e-3), "flops_per_step": flops,
+            "tflops": flops / (ms * 1e-3) / 1e12, "fp32_mfma_frac": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"]}
 
 
 def precision_study(torch, B, I, steps):
@@ -305,9 +410,12 @@ def main():
     ap.add_argument("--no-group", action="store_true", help="skip the several-collider measurement")
     ap.add_argument("--no-study", action="store_true", help="skip the 512-wide precision study")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-workload latency")
+    ap.add_argument("--no-fit", action="store_true", help="skip the fitting-step measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration) and exit")
     ap.add_argument("--copy-mib", type=int, default=256, help="size of the copy probe the counters saw")
+    ap.add_argument("--pmc-summary", metavar="DIR",
+                    help="only print the markdown summary of the rocprofv3 counter passes under DIR and exit")
     ap.add_argument("--traffic-from", nargs=4, metavar=("COPY_FETCH", "COPY_WRITE", "FETCH", "WRITE"),
                     help="only write the traffic record from four rocprofv3 --pmc counter CSVs and exit")
     args = ap.parse_args()
@@ -315,9 +423,11 @@ def main():
         copy_probe(args.copy_probe_mib)
         return
     if args.traffic_from:
-        traffic_record(*args.traffic_from, kernel="sdf_k16<256, %d, 2, 0>" % {"bf16": 1, "fp16": 2, "bf16x3": 3, "fp8": 4}[
-            args.precision], precision=args.precision, out=TRAFFIC_FILE,
-            copy_mib=args.copy_mib)
+        traffic_record(*args.traffic_from, kernel=K16_NAME % PREC_ID[args.precision], precision=args.precision,
+                       out=TRAFFIC_FILE, copy_mib=args.copy_mib)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, ["bf16", "fp16", "bf16x3", "fp8", "fp32"])
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the collision path shards across GPUs with no exchange "
@@ -360,6 +470,7 @@ def main():
         del X
 
     latency = None if args.no_latency else latency_small(torch, B, I)
+    fit = None if args.no_fit else fitting(torch, B, I, max(3, args.steps // 4))
     group = None if args.no_group else colliders(torch, B, I, args.steps)
     study = None if args.no_study else precision_study(torch, B, I, max(3, args.steps // 4))
     head = results[args.precision]
@@ -396,6 +507,8 @@ def main():
     }
     if latency:
         out["latency_sphere64"] = latency
+    if fit:
+        out["fitting"] = fit
     if group:
         out["colliders"] = group
     if study:

@@ -26,8 +26,9 @@ __global__ void pack_fp32_kernel(TrainNet t, const float* P, float* stream, floa
 __global__ void verlet_kernel(float* x, float* xp, int64_t m, float k, float c0, float c1, float c2);
 __global__ void fill_kernel(float* p, int64_t n, float v);
 __global__ void loss_reduce_kernel(const float* terms, int64_t n, float* loss);
-__global__ void wgrad_kernel(TrainNet t, const float* E, const float* H, const float* U, int64_t n,
-                             float* grad);
+__global__ void wgrad_kernel(TrainNet t, const float* E, const float* H, const float* U, int64_t n, int items,
+                             int nsplit, float* part, float* grad);
+__global__ void wgrad_reduce_kernel(TrainNet t, const float* part, int items, int nsplit, float* grad);
 }  // namespace sdfc
 
 using namespace sdfc;
@@ -657,9 +658,17 @@ namespace {
 constexpr int64_t kTrainChunk = 65536;  // points per chunk of a fitting step
 
 struct TrainLayout {  // byte offsets inside the caller's workspace
-  size_t stream, small, scratch, E, H, U, loss, total;
+  size_t stream, small, scratch, E, H, U, loss, part, total;
   int64_t chunk;
+  int items, nsplit;  // weight-gradient work items and point slices per item
 };
+
+// Work items of the weight-gradient contraction (wgrad_kernel): 64-row blocks
+// of every layer times 64-column blocks plus the 16-wide tail block.
+int wgrad_items(int W, int L) {
+  const int RB = W / 64, CB = W / 64 + 1;
+  return RB + (L - 1) * RB * CB + CB;
+}
 
 }  // namespace
 
@@ -671,9 +680,13 @@ namespace {
 // Chunk of a batch of n points for a workspace sized for at most max_chunk.
 int64_t train_chunk(int64_t n, int64_t max_chunk) { return n < max_chunk ? (n > 0 ? n : 1) : max_chunk; }
 
-TrainLayout train_layout(int W, int L, int64_t chunk, int slots) {
+// nsplit: point slices of the weight-gradient contraction (1: no partial
+// buffer, the slices' sums go straight into the gradient).
+TrainLayout train_layout(int W, int L, int64_t chunk, int slots, int nsplit) {
   TrainLayout t{};
   auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  t.items = wgrad_items(W, L);
+  t.nsplit = nsplit;
   size_t o = 0;
   t.stream = o;
   o = up(o + 2 * (size_t)(L - 1) * (W / 16) * (W / 16) * kFrag);
@@ -689,9 +702,18 @@ TrainLayout train_layout(int W, int L, int64_t chunk, int slots) {
   o = up(o + (size_t)chunk * 16 * 4);
   t.loss = o;
   o = up(o + (size_t)chunk * 4);
+  t.part = o;
+  if (nsplit > 1) o = up(o + (size_t)nsplit * t.items * 4096 * 4);
   t.total = o;
   t.chunk = chunk;
   return t;
+}
+
+// Point slices per weight-gradient work item: enough workgroups to fill the
+// GPU several times over, slices of at least 1024 points of a full chunk.
+int wgrad_splits(int W, int L, int cus) {
+  const int s = 8 * cus / wgrad_items(W, L);
+  return s < 1 ? 1 : (s > 64 ? 64 : s);
 }
 
 int train_check(const sdf_net_desc* desc, int* W, int* L, int* skip) {
@@ -778,8 +800,8 @@ int train_run(const sdf_net_desc* desc, int W, int L, int skip, const float* par
   a.delta = delta;
   a.inv_n = (float)(1.0 / (double)n);
   a.inv_kappa = 1.0f / t.kappa;
-  const int RB = W / 64 > 0 ? W / 64 : 1, CB = W / 64 + 1;
-  const int items = RB + (L - 1) * RB * CB + CB;
+  const int items = lay.items, nsplit = lay.nsplit;
+  float* part = (float*)(ws + lay.part);
   for (int64_t c0 = 0; c0 < n; c0 += lay.chunk) {
     const int64_t cn = std::min<int64_t>(lay.chunk, n - c0);
     a.pts_in = pts + 3 * c0;
@@ -791,7 +813,11 @@ int train_run(const sdf_net_desc* desc, int W, int L, int skip, const float* par
   if (W == WW) hipLaunchKernelGGL((sdf_k32<WW, MODE_TRAIN>), grid, dim3(kBlock), 0, s, a);
     KT(64) KT(128) KT(256)
 #undef KT
-    hipLaunchKernelGGL(wgrad_kernel, dim3(items), dim3(256), 0, s, t, a.ws_E, a.ws_H, a.ws_U, cn, grad_params);
+    hipLaunchKernelGGL(wgrad_kernel, dim3(items * nsplit), dim3(256), 0, s, t, a.ws_E, a.ws_H, a.ws_U, cn, items,
+                       nsplit, part, grad_params);
+    if (nsplit > 1)
+      hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((items * 4096 + 255) / 256), dim3(256), 0, s, t, part, items,
+                         nsplit, grad_params);
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, s, a.ws_loss, cn, loss);
   }
   const hipError_t e = hipGetLastError();
@@ -832,7 +858,7 @@ int64_t sdf_train_workspace_bytes(const sdf_net_desc* desc, int64_t n) {
   int W, L, skip, cus;
   if (train_check(desc, &W, &L, &skip) != SDF_OK || n < 0) return -1;
   if (device_cus(&cus) != SDF_OK) return -1;
-  return (int64_t)train_layout(W, L, train_chunk(n, kTrainChunk), cus).total;
+  return (int64_t)train_layout(W, L, train_chunk(n, kTrainChunk), cus, wgrad_splits(W, L, cus)).total;
 }
 
 int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* pts,
@@ -847,7 +873,7 @@ int sdf_train_step(const sdf_net_desc* desc, const float* params, const float* p
   int cus;
   rc = device_cus(&cus);
   if (rc) return rc;
-  const TrainLayout lay = train_layout(W, L, train_chunk(n, kTrainChunk), cus);
+  const TrainLayout lay = train_layout(W, L, train_chunk(n, kTrainChunk), cus, wgrad_splits(W, L, cus));
   if (n > 0 && workspace_bytes < lay.total)
     return fail(SDF_EINVAL, "workspace too small: need " + std::to_string(lay.total) + " bytes");
   return train_run(desc, W, L, skip, params, pts, target, n, delta, grad_params, loss,
@@ -874,9 +900,9 @@ int sdf_train_step_noalloc(const sdf_net_desc* desc, const float* params, const 
   // the largest chunk (a multiple of the tile) whose workspace fits the scratch
   int64_t chunk = std::min<int64_t>(train_chunk(n, kTrainChunk), kTrainChunk);
   chunk = (chunk + kPtsPerBlock - 1) / kPtsPerBlock * kPtsPerBlock;
-  while (chunk > kPtsPerBlock && train_layout(W, L, chunk, slots).total > kStaticScratchBytes)
+  while (chunk > kPtsPerBlock && train_layout(W, L, chunk, slots, 1).total > kStaticScratchBytes)
     chunk -= kPtsPerBlock;
-  const TrainLayout lay = train_layout(W, L, chunk, slots);
+  const TrainLayout lay = train_layout(W, L, chunk, slots, 1);
   if (lay.total > kStaticScratchBytes)
     return fail(SDF_EUNSUPPORTED, "network too large for the static scratch: one tile needs " +
                                       std::to_string(lay.total) + " bytes of " +

@@ -88,49 +88,79 @@ __global__ void __launch_bounds__(256) loss_reduce_kernel(const float* __restric
   if (threadIdx.x == 0) loss[0] += part[0];
 }
 
-// grad += sum_p E[p][rows] (x) H[p][cols] for one (layer, row block, column
-// block) work item.  Hidden layer l (1..L): E = e_l [n][W], H = H_{l-1}
-// [n][W+16] whose columns are h_{l-1} (W), x, y, z, 1, zeros.  Output layer
-// (l = L+1): E = dLoss/df [n][16] (row 0), H = H_L.  Columns map to
-// dW_l (hidden and skip x-columns), db_l (the "1" column), dw_o and db_o.
-__global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __restrict__ E,
-                                                    const float* __restrict__ H,
-                                                    const float* __restrict__ U, int64_t n,
-                                                    float* __restrict__ grad) {
+// Work item `item` of the weight-gradient contraction: hidden layer l
+// (1..L) or the output layer (l = L + 1), a block of 64 output rows and a
+// block of 64 input columns (or the 16-wide tail block: x, y, z, 1, zeros).
+struct WItem {
+  int l, rb, cb;
+};
+
+__device__ __forceinline__ WItem wgrad_item(const TrainNet& t, int item) {
   const int W = t.W, L = t.L;
   const int RB = W / 64, CB = W / 64 + 1;  // row blocks of 64; column blocks of 64 + the 16-wide tail
-  // decode the work item
-  int item = blockIdx.x;
-  int l, rb, cb;
-  if (item < RB) {  // layer 1: tail columns only
-    l = 1;
-    rb = item;
-    cb = CB - 1;
-  } else if ((item -= RB) < (L - 1) * RB * CB) {
-    l = 2 + item / (RB * CB);
-    rb = (item / CB) % RB;
-    cb = item % CB;
-  } else {
-    item -= (L - 1) * RB * CB;
-    l = L + 1;
-    rb = 0;
-    cb = item;
+  if (item < RB) return {1, item, CB - 1};  // layer 1: tail columns only
+  item -= RB;
+  if (item < (L - 1) * RB * CB) return {2 + item / (RB * CB), (item / CB) % RB, item % CB};
+  item -= (L - 1) * RB * CB;
+  return {L + 1, 0, item};
+}
+
+// Flat-parameter index of the gradient of output row j, input column k of
+// layer l (k < W: hidden input; W..W+2: x, y, z; W+3: bias), or -1.
+__device__ __forceinline__ int64_t wgrad_dst(const TrainNet& t, int l, int j, int k) {
+  const int W = t.W, L = t.L;
+  if (l == L + 1) {  // output layer: one real row
+    if (j != 0) return -1;
+    return (k < W) ? t.offo + k : (k == W + 3 ? t.offo + W : -1);
   }
+  if (k < W) return t.offW[l] + (int64_t)j * t.K(l) + k;  // hidden input columns (l >= 2)
+  if (k < W + 3) {
+    const int c = k - W;
+    if (l == 1) return t.offW[1] + 3 * j + c;
+    if (l == t.skip) return t.offW[l] + (int64_t)j * t.K(l) + W + c;
+    return -1;
+  }
+  if (k == W + 3) return t.offb[l] + j;
+  return -1;
+}
+
+// sum_p E[p][rows] (x) H[p][cols] for one work item over one slice of the
+// chunk's points.  Hidden layer l (1..L): E = e_l [n][W], H = H_{l-1}
+// [n][W+16] whose columns are h_{l-1} (W), x, y, z, 1, zeros.  Output layer
+// (l = L+1): E = dLoss/df [n][16] (row 0), H = H_L.  Columns map to dW_l
+// (hidden and skip x-columns), db_l (the "1" column), dw_o and db_o.
+// Workgroup b takes item b % items and point slice b / items of nsplit
+// equal slices.  nsplit == 1: grad += the sum directly (one owner per
+// element); otherwise the block is written to part[slice][item][64][64] and
+// wgrad_reduce_kernel adds the slices in a fixed order.
+__global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __restrict__ E,
+                                                    const float* __restrict__ H,
+                                                    const float* __restrict__ U, int64_t n, int items,
+                                                    int nsplit, float* __restrict__ part,
+                                                    float* __restrict__ grad) {
+  const int W = t.W, L = t.L;
+  const int item = blockIdx.x % items, slice = blockIdx.x / items;
+  const WItem wi = wgrad_item(t, item);
+  const int l = wi.l, CB = W / 64 + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const bool out_layer = (l == L + 1);
-  const bool tail = (cb == CB - 1);
+  const bool tail = (wi.cb == CB - 1);
   const int ncb = tail ? 1 : 4;  // N-tiles of 16 in this block
-  const int col0 = tail ? W : 64 * cb;
+  const int col0 = tail ? W : 64 * wi.cb;
   // rows of this wave: 16 per wave (the output layer has one real row: wave 0)
   if (out_layer && wave > 0) return;
-  const int row0 = 64 * rb + 16 * wave;
+  const int row0 = 64 * wi.rb + 16 * wave;
   const float* Eb = out_layer ? U : E + (size_t)(l - 1) * n * W;
   const int es = out_layer ? 16 : W;
   const float* Hb = H + (size_t)(l - 1) * n * (W + 16);
   const int hs = W + 16;
+  // this slice's points, in steps of 4 (one MFMA K-step)
+  const int64_t steps = (n + 3) / 4;
+  const int64_t p_lo = 4 * (steps * slice / nsplit), p_hi = 4 * (steps * (slice + 1) / nsplit);
   f32x4 acc[4] = {};
-  for (int64_t p0 = 0; p0 < n; p0 += 4) {
+#pragma unroll 4
+  for (int64_t p0 = p_lo; p0 < p_hi; p0 += 4) {
     const int64_t p = p0 + g;
     const bool ok = p < n;
     const float a = ok ? Eb[p * es + (out_layer ? c16 : row0 + c16)] : 0.0f;
@@ -144,26 +174,38 @@ __global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __r
   }
   // acc[nt][i] = sum_p E[p][row0 + 4g + i] H[p][col0 + 16 nt + c16]
   for (int nt = 0; nt < ncb; ++nt) {
-    const int k = col0 + 16 * nt + c16;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int j = (out_layer ? 0 : row0) + 4 * g + i;
       const float v = acc[nt][i];
-      int64_t dst = -1;
-      if (out_layer) {
-        if (j == 0) dst = (k < W) ? t.offo + k : (k == W + 3 ? t.offo + W : -1);
-      } else if (k < W) {
-        dst = t.offW[l] + (int64_t)j * t.K(l) + k;  // hidden input columns (l >= 2)
-      } else if (k < W + 3) {
-        const int c = k - W;
-        if (l == 1) dst = t.offW[1] + 3 * j + c;
-        else if (l == t.skip) dst = t.offW[l] + (int64_t)j * t.K(l) + W + c;
-      } else if (k == W + 3) {
-        dst = t.offb[l] + j;
+      if (nsplit > 1) {
+        const int r = 16 * wave + 4 * g + i, c = 16 * nt + c16;
+        part[(((size_t)slice * items + item) * 64 + r) * 64 + c] = v;
+      } else {
+        const int j = (out_layer ? 0 : row0) + 4 * g + i;
+        const int64_t dst = wgrad_dst(t, l, j, col0 + 16 * nt + c16);
+        if (dst >= 0) grad[dst] += v;
       }
-      if (dst >= 0) grad[dst] += v;
     }
   }
+}
+
+// grad += sum over the nsplit slices (in slice order) of every work item's
+// 64 x 64 block; one thread per block element.
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(TrainNet t, const float* __restrict__ part,
+                                                           int items, int nsplit, float* __restrict__ grad) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)items * 4096) return;
+  const int item = (int)(idx >> 12), r = (int)((idx >> 6) & 63), c = (int)(idx & 63);
+  const WItem wi = wgrad_item(t, item);
+  const int W = t.W, CB = W / 64 + 1;
+  const bool out_layer = (wi.l == t.L + 1), tail = (wi.cb == CB - 1);
+  if ((tail && c >= 16) || (out_layer && r >= 16)) return;  // never written
+  const int j = out_layer ? r : 64 * wi.rb + r;
+  const int64_t dst = wgrad_dst(t, wi.l, j, (tail ? W : 64 * wi.cb) + c);
+  if (dst < 0) return;
+  float s = 0.0f;
+  for (int q = 0; q < nsplit; ++q) s += part[(((size_t)q * items + item) * 64 + r) * 64 + c];
+  grad[dst] += s;
 }
 
 }  // namespace sdfc

@@ -106,3 +106,48 @@ def test_fitting_reduces_the_loss_on_a_displaced_icosphere():
         losses.append(float(loss))
     print("fit loss %.4g -> %.4g" % (losses[0], losses[-1]))
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_fitted_net_has_unit_gradient_near_the_surface():
+    """A net fitted to brute-force signed distances of the displaced icosphere
+    is SDF-like near the surface: for fresh near-surface points with |f| <
+    0.05 the median of | |grad f| - 1 | is below 0.05 (an SDF has unit
+    gradient almost everywhere), evaluated by the FP64 oracle on the fitted
+    parameters and by the FP32 kernel.  The geometric initialisation alone
+    is checked to be farther off, so the fit is what brings it there."""
+    V, F = I.displaced_icosphere(level=3, seed=3)
+    pts = I.training_samples(V, F, 32768, seed=4)
+    tgt = oracle.mesh_sdf(V, F, pts).astype(np.float32)
+    spec = I.NetSpec((128,) * 4, 2)
+    p0 = I.init_geometric(spec, 0)
+    P = torch.from_numpy(p0).cuda().requires_grad_(True)
+    X, S = torch.from_numpy(pts).cuda(), torch.from_numpy(tgt).cuda()
+    fit = B.SdfFit(spec, len(pts))
+    opt = torch.optim.Adam([P], lr=1e-3)
+    for it in range(2500):  # about 1.5 s on one MI355X
+        opt.zero_grad()
+        loss = B.fit_loss(fit, P, X, S, 0.1)
+        loss.backward()
+        opt.step()
+    rng = np.random.default_rng(11)
+    Q = np.ascontiguousarray(I.surface_samples(V, F, 8192, rng, sigma=0.01).astype(np.float32))
+    pf = P.detach().cpu().numpy()
+
+    def band_stat(params):
+        f, g = oracle.mlp_eval(spec, params, Q)
+        near = np.abs(f) < 0.05
+        return float(np.median(np.abs(np.linalg.norm(g[near], axis=1) - 1.0))), near.mean()
+
+    fitted, frac = band_stat(pf)
+    initial, _ = band_stat(p0)
+    net = B.SdfNet(spec, pf, "fp32")
+    fq, gq = net.query_grad(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    fq, gq = fq.cpu().numpy(), gq.cpu().numpy().astype(np.float64)
+    near = np.abs(fq) < 0.05
+    gpu = float(np.median(np.abs(np.linalg.norm(gq[near], axis=1) - 1.0)))
+    net.close()
+    print("| |grad f| - 1 | median near the surface: fitted %.4f (kernel %.4f, %.0f%% of points), initial %.4f, "
+          "final loss %.4g" % (fitted, gpu, 100 * frac, initial, float(loss)))
+    assert fitted < 0.05 and gpu < 0.05
+    assert initial > fitted

@@ -173,11 +173,21 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   // LDS byte offset of this lane's half-fragment for global M-tile of local mt, tile ct
   auto act_off = [&](int mt, int ct) {
     const int m = MTW * wave + mt;
-    if constexpr (F8)
-      return ((m >> 3) * NCT + ct) * G::FRAG + lane * 32 + 4 * (m & 7);
-    else
-      return ((m >> 1) * NCT + ct) * kFrag + lane * 16 + 8 * (m & 1);
+    return ((m >> 1) * NCT + ct) * kFrag + lane * 16 + 8 * (m & 1);
   };
+  // FP8 exchange layout: the fragment of (K-block of 128, column tile) is
+  // 8 / MTW planes of 64 lanes x 4 MTW bytes; plane p holds the operand bytes
+  // of M-tiles 8 kb + p MTW .. 8 kb + p MTW + MTW - 1 (one wave's rows), so a
+  // wave writes one contiguous 4 MTW-byte chunk per lane (free of bank
+  // conflicts), and a lane's 32-byte B operand is its chunks of the 8 / MTW
+  // planes in plane order.
+  constexpr int PW = 4 * MTW;     // bytes per lane per plane
+  constexpr int NPL = 32 / PW;    // planes per fragment
+  auto f8_off = [&](int ct) {
+    const int m0 = MTW * wave;
+    return ((m0 >> 3) * NCT + ct) * G::FRAG + ((m0 & 7) / MTW) * 64 * PW + lane * PW;
+  };
+  unsigned f8w[F8 ? NCT : 1][F8 ? MTW : 1];  // E4M3 words of the wave's M-tiles, per column tile
   // The wave's rows cover whole K-blocks of the next contraction when MTW is
   // even: K-block kb0 + j holds local M-tiles 2j, 2j + 1 (see act_off).
   constexpr int NOWN = (SDF_K16_OWN && NS == 1 && !F8 && W != 512 && MTW % 2 == 0) ? MTW / 2 : 0;
@@ -224,7 +234,18 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   // keep_l: stack layer to record v in (0: none).
   auto put = [&](unsigned char* out, int mt, int ct, f32x4 v, int keep_l) {
     if constexpr (F8) {
-      *reinterpret_cast<unsigned*>(out + act_off(mt, ct)) = pack4_fp8(keep_l > 0 ? v * 0.25f : v);
+      f8w[ct][mt] = pack4_fp8(keep_l > 0 ? v * 0.25f : v);
+      if (mt == MTW - 1) {  // the wave's chunk of this column tile is complete
+        unsigned char* dst = out + f8_off(ct);
+        if constexpr (MTW == 1) {
+          *reinterpret_cast<unsigned*>(dst) = f8w[ct][0];
+        } else if constexpr (MTW == 2) {
+          *reinterpret_cast<uint2*>(dst) = uint2{f8w[ct][0], f8w[ct][1]};
+        } else {
+          static_assert(MTW == 4, "FP8 chunk");
+          *reinterpret_cast<u32x4*>(dst) = u32x4{f8w[ct][0], f8w[ct][1], f8w[ct][2], f8w[ct][3]};
+        }
+      }
       if (keep_l > 0) {
         const uint2 q = pack4<PREC_BF16>(v);
         if (keep_l <= G::LS)
@@ -359,11 +380,31 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     AT Bv[2][NCT][NS];  // B operands of K-steps j (in use) and j + 1 (in flight)
     auto loadB = [&](AT (&dst)[NCT][NS], int j) {
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct)
+      for (int ct = 0; ct < NCT; ++ct) {
+        if constexpr (F8) {  // the lane's chunks of the NPL planes
+          const unsigned char* src = in + (kbi(j) * NCT + ct) * G::FRAG + lane * PW;
 #pragma unroll
-        for (int ps = 0; ps < NS; ++ps)
-          dst[ct][ps] = *reinterpret_cast<const AT*>(in + ps * G::ACT_BYTES + (kbi(j) * NCT + ct) * G::FRAG +
-                                                     lane * (int)sizeof(AT));
+          for (int pl = 0; pl < NPL; ++pl) {
+            const unsigned char* c = src + pl * 64 * PW;
+            if constexpr (MTW == 1) {
+              dst[ct][0][pl] = *reinterpret_cast<const unsigned*>(c);
+            } else if constexpr (MTW == 2) {
+              const uint2 w = *reinterpret_cast<const uint2*>(c);
+              dst[ct][0][2 * pl] = w.x;
+              dst[ct][0][2 * pl + 1] = w.y;
+            } else {
+              const u32x4 w = *reinterpret_cast<const u32x4*>(c);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) dst[ct][0][4 * pl + e] = w[e];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int ps = 0; ps < NS; ++ps)
+            dst[ct][ps] = *reinterpret_cast<const AT*>(in + ps * G::ACT_BYTES + (kbi(j) * NCT + ct) * G::FRAG +
+                                                       lane * (int)sizeof(AT));
+        }
+      }
     };
     loadB(Bv[0], NOWN);
 #pragma unroll

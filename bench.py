@@ -218,8 +218,10 @@ def spread(per):
 
 def colliders(torch, B, I, steps, precision="bf16"):
     """Several colliders (16 networks of widths 128-512, depths 4-8, 4M cloth
-    vertices in patches of uneven size): one grouped launch per width class,
-    against one call per network, and thirty grouped passes in one HIP graph."""
+    vertices in patches of uneven size): one call per network, one launch per
+    width class and one persistent launch per pass, timed in three
+    interleaved rounds after a warm-up (median per mode); thirty passes of the
+    default launch in one HIP graph; and the autotuner's pick."""
     cs = I.collider_set()
     eps = 0.005
     nets = [B.SdfNet(c["spec"], c["params"], precision) for c in cs]
@@ -240,25 +242,34 @@ def colliders(torch, B, I, steps, precision="bf16"):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / k
 
-    ms_group = timed(grp.collide_project, steps)
-    ms_single = timed(lambda: [B.collide_project(net.handle, x, x.shape[0], eps) for net, x in zip(nets, X)],
-                      steps)
+    modes = ("per_network", "per_width", "persistent")
+    timed(grp.collide_project, 3 * steps)  # warm-up: clocks settle before the first timed mode
+    runs = {m: [] for m in modes}
+    for rnd in range(3):
+        for mode in (modes if rnd % 2 == 0 else modes[::-1]):
+            grp.set_launch(mode)
+            runs[mode].append(timed(grp.collide_project, steps))
+    ms = {m: sorted(v)[1] for m, v in runs.items()}
+    grp.set_launch("per_network")
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         for _ in range(30):
             grp.collide_project()
     ms_graph = timed(graph.replay, max(1, steps // 10)) / 30
     del graph
-    per_net = grp.autotune()
+    mode = grp.autotune()
     ms_tuned = timed(grp.collide_project, steps)
     grp.close()
     for net in nets:
         net.close()
+    best = min(ms, key=ms.get)
     return {"workload": "16 colliders, widths 128/256/512, depths 4-8, %d vertices, seed 5" % n,
             "precision": precision, "points": n,
-            "grouped_ms": ms_group, "per_network_ms": ms_single, "graph_30_passes_ms_per_pass": ms_graph,
-            "autotuned_ms": ms_tuned, "autotuned_launch": "per network" if per_net else "per width class",
-            "grouped_points_per_s": n / (ms_group * 1e-3), "grouped_tflops": flops / (ms_group * 1e-3) / 1e12}
+            "per_network_ms": ms["per_network"], "per_width_ms": ms["per_width"], "persistent_ms": ms["persistent"],
+            "graph_30_per_network_passes_ms_per_pass": ms_graph,
+            "autotuned_ms": ms_tuned, "autotuned_launch": {0: "per_width", 1: "per_network", 2: "persistent"}[mode],
+            "best_launch": best, "points_per_s": n / (ms[best] * 1e-3),
+            "tflops": flops / (ms[best] * 1e-3) / 1e12}
 
 
 def fitting(torch, B, I, steps, warmup=2, n=1_000_000):

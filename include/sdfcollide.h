@@ -158,10 +158,30 @@ typedef struct sdf_group sdf_group; /* opaque; device tables of a fixed set of c
 int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts,
                      const int64_t* counts, float eps, sdf_group** out);
 
+/* How a pass is launched (sdf_group_set_launch, sdf_group_autotune):
+ * SDF_GROUP_PER_WIDTH   one launch per hidden width present, every workgroup
+ *                       taking one tile of one network (deeper networks first);
+ * SDF_GROUP_PER_NETWORK one collide_project launch per network;
+ * SDF_GROUP_PERSISTENT  one launch of one workgroup per compute unit for the
+ *                       whole pass: workgroups take (network, tile) work items
+ *                       from a device counter, network after network in order
+ *                       of decreasing cost per tile, until none are left (needs
+ *                       every member of width 128 or more, 512 members at
+ *                       most).
+ * A new group uses SDF_GROUP_PER_NETWORK.  Every mode computes the same bits
+ * per vertex. */
+enum { SDF_GROUP_PER_WIDTH = 0, SDF_GROUP_PER_NETWORK = 1, SDF_GROUP_PERSISTENT = 2 };
+
 /* One collide_project pass over every (network, vertex buffer) pair of the
- * group: one kernel launch per hidden width present, every workgroup taking
- * one tile of one network (deeper networks' tiles first).  No allocation. */
+ * group, launched as the group's mode says.  No allocation; the persistent
+ * launch resets its own counters at the end of the pass, so the pass can be
+ * captured into a HIP graph and replayed.  Passes of one group must not
+ * overlap in time (they share the counters): issue them on one stream. */
 int sdf_group_collide_project(const sdf_group* grp, void* stream);
+
+/* Sets the launch mode (SDF_GROUP_*).  SDF_EUNSUPPORTED for
+ * SDF_GROUP_PERSISTENT when a member is narrower than 128. */
+int sdf_group_set_launch(sdf_group* grp, int mode);
 
 /* Frees the group's device tables (not the networks or buffers). */
 int sdf_group_destroy(sdf_group* grp);
@@ -179,15 +199,15 @@ int sdf_group_destroy(sdf_group* grp);
  *
  * sdf_group_autotune times, on scratch copies of the members' vertices (the
  * members are not moved), each width class's tile variants inside the
- * grouped launch and then one launch per width class against one launch per
- * network, and keeps the faster configuration for sdf_group_collide_project.
- * *per_network (nullable) receives 1 when per-network launches were chosen.
- * Allocates and frees its scratch; synchronous on `stream`. */
+ * per-width launch and then the three launch modes (SDF_GROUP_*), and keeps
+ * the fastest for sdf_group_collide_project.  *mode (nullable) receives the
+ * chosen SDF_GROUP_* mode.  Allocates and frees its scratch; synchronous on
+ * `stream`. */
 int sdf_net_autotune(sdf_net* net, int64_t n_sample, void* stream, int* variant);
 /* Sets the tile variant directly (e.g. a cached autotune result): 0 always,
  * 1 where sdf_net_autotune has a choice (else SDF_EUNSUPPORTED). */
 int sdf_net_set_tile_variant(sdf_net* net, int variant);
-int sdf_group_autotune(sdf_group* grp, void* stream, int* per_network);
+int sdf_group_autotune(sdf_group* grp, void* stream, int* mode);
 
 /* ---- the time step between collision passes (Sec. 4.1: explicit Verlet) ----
  *

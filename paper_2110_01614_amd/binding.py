@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(HERE, "libsdfcollide.so")
 SDF_OK, SDF_EINVAL, SDF_EUNSUPPORTED, SDF_ENOMEM, SDF_EDEVICE = 0, -1, -2, -3, -4
 SDF_FP32, SDF_BF16, SDF_FP16, SDF_BF16X3, SDF_FP8 = 0, 1, 2, 3, 4
 SDF_MAX_HIDDEN = 16
+SDF_GROUP_PER_WIDTH, SDF_GROUP_PER_NETWORK, SDF_GROUP_PERSISTENT = 0, 1, 2
+GROUP_MODES = {"per_width": SDF_GROUP_PER_WIDTH, "per_network": SDF_GROUP_PER_NETWORK,
+               "persistent": SDF_GROUP_PERSISTENT}
 PRECISIONS = {"fp32": SDF_FP32, "bf16": SDF_BF16, "fp16": SDF_FP16, "bf16x3": SDF_BF16X3, "fp8": SDF_FP8}
 
 
@@ -99,6 +102,8 @@ def _load():
     lib.sdf_net_autotune.argtypes = [vp, i64, vp, ctypes.POINTER(ctypes.c_int)]
     lib.sdf_net_set_tile_variant.restype = ctypes.c_int
     lib.sdf_net_set_tile_variant.argtypes = [vp, ctypes.c_int]
+    lib.sdf_group_set_launch.restype = ctypes.c_int
+    lib.sdf_group_set_launch.argtypes = [vp, ctypes.c_int]
     lib.sdf_group_autotune.restype = ctypes.c_int
     lib.sdf_group_autotune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int)]
     lib.sdf_verlet_step.restype = ctypes.c_int
@@ -383,9 +388,14 @@ def sdf_net_autotune(handle, n_sample=1 << 18, stream=None) -> int:
 
 
 def sdf_group_autotune(group, stream=None) -> int:
+    """Times the launch modes and keeps the fastest; returns its SDF_GROUP_* value."""
     v = ctypes.c_int(0)
     _check(lib.sdf_group_autotune(group, _stream(stream), ctypes.byref(v)))
     return v.value
+
+
+def sdf_group_set_launch(group, mode):
+    return _check(lib.sdf_group_set_launch(group, GROUP_MODES.get(mode, mode)))
 
 
 def verlet_step(pts, prev, dt, gravity=(0.0, 0.0, -9.81), damping=0.0, stream=None):
@@ -414,8 +424,12 @@ class SdfGroup:
         sdf_group_collide_project(self.handle, stream)
 
     def autotune(self, stream=None) -> int:
-        """Pick tile variants and launch shape by timing; returns 1 for per-network launches."""
+        """Pick tile variants and the launch mode by timing; returns the SDF_GROUP_* mode."""
         return sdf_group_autotune(self.handle, stream)
+
+    def set_launch(self, mode):
+        """"per_width", "per_network" or "persistent" (or an SDF_GROUP_* value)."""
+        sdf_group_set_launch(self.handle, mode)
 
     def close(self):
         if self.handle:

@@ -21,10 +21,13 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # (source, extra defines, object name)
 # 16-bit kernel instantiations: (hidden width, operand type: 1 BF16, 2 FP16,
-# 3 BF16x3, 4 FP8); FP8 exists from width 128
+# 3 BF16x3, 4 FP8); FP8 exists from width 128; the persistent grouped kernel
+# (all widths 128-512 in one kernel) per operand type
 K16_UNITS = [(w, p) for w in (64, 128, 256, 512) for p in (1, 2, 3, 4) if not (w == 64 and p == 4)]
 UNITS = [("sdf_k16.hip", ["-DSDF_K16_WIDTH=%d" % w, "-DSDF_K16_PREC=%d" % p], "sdf_k16_w%d_p%d" % (w, p))
          for w, p in sorted(K16_UNITS, key=lambda u: -u[0])] + \
+        [("sdf_k16.hip", ["-DSDF_K16_PERSIST", "-DSDF_K16_WIDTH=0", "-DSDF_K16_PREC=%d" % p], "sdf_k16_persist_p%d" % p)
+         for p in (1, 2, 3, 4)] + \
         [(s, [], os.path.splitext(s)[0]) for s in ("sdf_api.cpp", "sdf_k32.hip", "sdf_train.hip", "sdf_step.hip")]
 
 FLAGS = [

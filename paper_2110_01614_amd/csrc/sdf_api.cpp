@@ -20,6 +20,8 @@ template <int W, int PREC, int MODE, int VAR>
 __global__ void sdf_k16(const KArgs a);
 template <int W, int PREC, int MODE, int VAR>
 __global__ void sdf_k16_group(const KArgs* nets, const int* tile_start, int n_nets, int tile0);
+template <int PREC>
+__global__ void sdf_k16_persist(const KArgs* nets, const int* width, const int* item_start, int n_nets, int* ctr);
 template <int W, int MODE>
 __global__ void sdf_k32(const KArgs a);
 __global__ void pack_fp32_kernel(TrainNet t, const float* P, float* stream, float* small);
@@ -918,7 +920,16 @@ int sdf_train_step_noalloc(const sdf_net_desc* desc, const float* params, const 
 struct sdf_group {
   int device = 0;
   int prec = 0;
-  int per_network = 0;  // 1: one launch per network instead of one per width (autotuner)
+  int mode = SDF_GROUP_PER_NETWORK;  // SDF_GROUP_*: how a pass is launched
+  // persistent launch (all members of width >= 128, at most 512 of them):
+  // members in work order, their widths, their first work items (n + 1), the
+  // two work counters; one workgroup per CU
+  bool persist_ok = false;
+  int cus = 0, n_persist = 0;
+  KArgs* d_pargs = nullptr;
+  int* d_pwidth = nullptr;
+  int* d_pstart = nullptr;
+  int* d_ctr = nullptr;
   struct Class {
     int W = 0, n = 0, var = 0;
     int tiles[2] = {0, 0};         // per tile variant
@@ -958,11 +969,26 @@ hipError_t launch_class(int prec, const sdf_group::Class& c, const KArgs* d_args
   return hipGetLastError();
 }
 
-// A whole pass: every class (grouped) or every network (per network), with the
-// class tables at `d_args`-relative positions of the group (off) or host args.
+// The persistent launch over tables (members in work order) with counters ctr.
+hipError_t launch_persist(int prec, int cus, const KArgs* d_args, const int* d_width, const int* d_start, int n,
+                          int* d_ctr, hipStream_t s) {
+  const dim3 grid((unsigned)cus), block(512);
+#define KP(PP) \
+  if (prec == PP) hipLaunchKernelGGL((sdf_k16_persist<PP>), grid, block, 0, s, d_args, d_width, d_start, n, d_ctr);
+  KP(PREC_BF16) KP(PREC_FP16) KP(PREC_BF16X3) KP(PREC_FP8)
+#undef KP
+  return hipGetLastError();
+}
+
+// A whole pass: one persistent launch, every class (grouped) or every network
+// (per network), with the class tables at `d_args`-relative positions of the
+// group (off) or host args.
 hipError_t group_pass(const sdf_group* grp, const KArgs* d_table, const std::vector<KArgs>& host_args,
                       hipStream_t s) {
-  if (grp->per_network) {
+  if (grp->mode == SDF_GROUP_PERSISTENT)
+    return launch_persist(grp->prec, grp->cus, grp->d_pargs, grp->d_pwidth, grp->d_pstart, grp->n_persist,
+                          grp->d_ctr, s);
+  if (grp->mode == SDF_GROUP_PER_NETWORK) {
     for (size_t i = 0; i < grp->nets.size(); ++i) {
       const hipError_t e = launch<MODE_PROJECT>(grp->nets[i], host_args[i], s);
       if (e != hipSuccess) return e;
@@ -1089,12 +1115,46 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
     c.tiles[1] = (int)tiles[1];
     grp->classes.push_back(c);
   }
+  // Persistent work order: members by decreasing cost of one tile (width^2 x
+  // depth x points per tile), then larger patches first; tile variant 0.
+  const int nm = (int)grp->args.size();
+  std::vector<int> order(nm);
+  for (int i = 0; i < nm; ++i) order[i] = i;
+  auto tile_cost = [&](int i) {
+    const sdf_net* n = grp->nets[i];
+    return (double)n->W * n->W * n->L * pts_per_tile(n->W, 0);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (tile_cost(x) != tile_cost(y)) return tile_cost(x) > tile_cost(y);
+    return grp->args[x].n > grp->args[y].n;
+  });
+  std::vector<KArgs> pargs;
+  std::vector<int> pwidth, pstart(1, 0);
+  bool persist_ok = nm > 0 && nm <= 512;  // the kernel keeps the item table in LDS
+  for (int q = 0; q < nm; ++q) {
+    const int i = order[q];
+    const int W = grp->nets[i]->W;
+    const int64_t next = pstart.back() + (grp->args[i].n + pts_per_tile(W, 0) - 1) / pts_per_tile(W, 0);
+    persist_ok = persist_ok && W >= 128 && next < 0x7fffffff;
+    pargs.push_back(grp->args[i]);
+    pwidth.push_back(W);
+    pstart.push_back((int)std::min<int64_t>(next, 0x7fffffff));
+  }
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(dev);
+  if (hipDeviceGetAttribute(&grp->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || grp->cus < 1) {
+    (void)hipSetDevice(prev);
+    sdf_group_destroy(grp);
+    return fail(SDF_EDEVICE, "hipDeviceGetAttribute(CU count)");
+  }
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
   const size_t abytes = grp->args.size() * sizeof(KArgs), sbytes = starts[0].size() * sizeof(int);
+  const size_t o_pargs = up(abytes + 2 * sbytes), o_pwidth = up(o_pargs + abytes),
+               o_pstart = up(o_pwidth + nm * sizeof(int)), o_ctr = up(o_pstart + (nm + 1) * sizeof(int)),
+               total = o_ctr + 256;
   if (!grp->args.empty()) {
-    if (hipMalloc(&grp->d_mem, abytes + 2 * sbytes + 256) != hipSuccess) {
+    if (hipMalloc(&grp->d_mem, total) != hipSuccess) {
       (void)hipSetDevice(prev);
       sdf_group_destroy(grp);
       return fail(SDF_ENOMEM, "hipMalloc(group tables)");
@@ -1102,7 +1162,11 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
     unsigned char* m = (unsigned char*)grp->d_mem;
     if (hipMemcpy(m, grp->args.data(), abytes, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(m + abytes, starts[0].data(), sbytes, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(m + abytes + sbytes, starts[1].data(), sbytes, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(m + abytes + sbytes, starts[1].data(), sbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m + o_pargs, pargs.data(), abytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m + o_pwidth, pwidth.data(), nm * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m + o_pstart, pstart.data(), (nm + 1) * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(m + o_ctr, 0, 256) != hipSuccess) {
       (void)hipSetDevice(prev);
       sdf_group_destroy(grp);
       return fail(SDF_EDEVICE, "hipMemcpy(group tables)");
@@ -1114,9 +1178,27 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
       c.d_start[1] = (int*)(m + abytes + sbytes) + off;
       off += c.n;
     }
+    grp->d_pargs = (KArgs*)(m + o_pargs);
+    grp->d_pwidth = (int*)(m + o_pwidth);
+    grp->d_pstart = (int*)(m + o_pstart);
+    grp->d_ctr = (int*)(m + o_ctr);
+    grp->n_persist = nm;
+    grp->persist_ok = persist_ok;
+    grp->mode = SDF_GROUP_PER_NETWORK;
   }
   (void)hipSetDevice(prev);
   *out = grp;
+  return SDF_OK;
+}
+
+int sdf_group_set_launch(sdf_group* grp, int mode) {
+  g_err.clear();
+  if (!grp) return fail(SDF_EINVAL, "group is NULL");
+  if (mode != SDF_GROUP_PER_WIDTH && mode != SDF_GROUP_PER_NETWORK && mode != SDF_GROUP_PERSISTENT)
+    return fail(SDF_EINVAL, "unknown launch mode");
+  if (mode == SDF_GROUP_PERSISTENT && !grp->persist_ok && !grp->classes.empty())
+    return fail(SDF_EUNSUPPORTED, "the persistent launch needs every member of width 128 or more, 512 at most");
+  grp->mode = mode;
   return SDF_OK;
 }
 
@@ -1185,7 +1267,7 @@ int sdf_net_set_tile_variant(sdf_net* net, int variant) {
   return SDF_OK;
 }
 
-int sdf_group_autotune(sdf_group* grp, void* stream, int* per_network) {
+int sdf_group_autotune(sdf_group* grp, void* stream, int* mode_out) {
   g_err.clear();
   if (!grp) return fail(SDF_EINVAL, "group is NULL");
   if (grp->classes.empty()) return SDF_OK;
@@ -1231,19 +1313,43 @@ int sdf_group_autotune(sdf_group* grp, void* stream, int* per_network) {
     }
     off += c.n;
   }
-  // 2) one launch per width class, or one per network (networks keep their own variant)
-  float t[2];
-  for (int m = 0; m < 2; ++m) {
-    grp->per_network = m;
-    refill();
-    t[m] = time_ms([&] { (void)group_pass(grp, d_tab, tmp, s); }, s, 3);
+  // 2) one launch per width class, one per network (networks keep their own
+  // variant) or one persistent launch over everything (tile variant 0)
+  std::vector<KArgs> ptmp(grp->n_persist);  // the persistent table over the scratch copies
+  KArgs* d_ptab = nullptr;
+  if (grp->persist_ok) {
+    if (e == hipSuccess) e = hipMemcpy(ptmp.data(), grp->d_pargs, ptmp.size() * sizeof(KArgs), hipMemcpyDeviceToHost);
+    for (auto& a : ptmp)
+      for (size_t i = 0; i < grp->args.size(); ++i)
+        if (grp->args[i].pts_in == a.pts_in) {
+          a.pts_in = tmp[i].pts_in;
+          a.pts_out = tmp[i].pts_out;
+        }
+    if (e == hipSuccess && hipMalloc(&d_ptab, ptmp.size() * sizeof(KArgs)) != hipSuccess) e = hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipMemcpy(d_ptab, ptmp.data(), ptmp.size() * sizeof(KArgs), hipMemcpyHostToDevice);
   }
-  grp->per_network = (t[1] > 0.0f && t[1] < t[0]) ? 1 : 0;
+  float t[3] = {-1.0f, -1.0f, -1.0f};
+  for (int m = 0; m < 3 && e == hipSuccess; ++m) {
+    if (m == SDF_GROUP_PERSISTENT && !grp->persist_ok) continue;
+    refill();
+    if (m == SDF_GROUP_PERSISTENT)
+      t[m] = time_ms([&] { (void)launch_persist(grp->prec, grp->cus, d_ptab, grp->d_pwidth, grp->d_pstart,
+                                                grp->n_persist, grp->d_ctr, s); }, s, 3);
+    else {
+      grp->mode = m;
+      t[m] = time_ms([&] { (void)group_pass(grp, d_tab, tmp, s); }, s, 3);
+    }
+  }
+  int best = SDF_GROUP_PER_WIDTH;
+  for (int m = 1; m < 3; ++m)
+    if (t[m] > 0.0f && (t[best] <= 0.0f || t[m] < t[best])) best = m;
+  grp->mode = best;
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(scratch);
   (void)hipFree(d_tab);
+  if (d_ptab) (void)hipFree(d_ptab);
   (void)hipSetDevice(prev);
-  if (per_network) *per_network = grp->per_network;
+  if (mode_out) *mode_out = grp->mode;
   return e == hipSuccess ? SDF_OK : hip_fail(e, "autotune");
 }
 

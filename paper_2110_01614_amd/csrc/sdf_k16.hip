@@ -64,6 +64,15 @@ struct GeoB {
   static constexpr int LAYER_BYTES = NWV * WAVE_BYTES;
   static constexpr int ACT_BYTES = KB * NCT * FRAG;        // one exchange buffer part
   static constexpr int NS_ = NS;
+  // LDS of one workgroup (byte offsets, 16-byte aligned): the double-buffered
+  // exchange buffers, the small FP32 block (17 W floats), the points, the
+  // LDS part of the reverse-sweep stack, the per-wave partial sums.
+  static constexpr int OFF_ACT = 0;
+  static constexpr int OFF_SM = OFF_ACT + 2 * NS * ACT_BYTES;
+  static constexpr int OFF_XS = OFF_SM + 17 * W * 4;
+  static constexpr int OFF_STK = OFF_XS + PTS * 16;
+  static constexpr int OFF_RED = OFF_STK + STK_BYTES;
+  static constexpr int LDS_BYTES = OFF_RED + NWV * PTS * 16;
   static_assert(MTW >= 1 && KB >= 1 && KB % R == 0, "shape");
 };
 
@@ -103,8 +112,12 @@ __device__ __forceinline__ void split4(f32x4 v, uint2& hi, uint2& lo) {
 
 // The whole per-workgroup pass over tile `tile` (points [tile PTS, tile PTS +
 // PTS) of a.pts_in) of network `a`.
+// LDS geometry of a (width, operand type, tile variant) configuration.
+template <int W, int PREC, int VAR>
+using GeoP = GeoB<W, PREC == PREC_BF16X3 ? 2 : 1, PREC == PREC_FP8, VAR>;
+
 template <int W, int PREC, int MODE, int VAR>
-__device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
+__device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char* lds, int tid) {
   constexpr int NS = PREC == PREC_BF16X3 ? 2 : 1;
   // FP8: E4M3 exchange operands (forward activations stored as r / 4), weights
   // scaled per layer by a power of two undone by a.fsc / a.rsc; the stack of r
@@ -117,19 +130,20 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
   constexpr SmallLayout SL{W};
   constexpr int MTW = G::MTW, KB = G::KB, NCT = G::NCT, R = G::R, PTS = G::PTS;
 
-  __shared__ __attribute__((aligned(16))) unsigned char act[2][NS][G::ACT_BYTES];
+  // LDS, carved from the caller's buffer of G::LDS_BYTES (16-byte aligned)
+  auto& act = *reinterpret_cast<unsigned char (*)[2][NS][G::ACT_BYTES]>(lds + G::OFF_ACT);
   // The small FP32 block in the compact form this kernel reads: [l1: 4W |
   // skf: 4W | wof: W | bias of layers 1..8: 8W]; the gradient copies of l1 and
   // skf and the reverse seed are these times per-network scalars (a.c_l1g,
   // a.c_skg, a.c_wob).  Layer 1's bias slot holds the Fourier net's bias.
   constexpr int C_L1 = 0, C_SKF = 4 * W, C_WOF = 8 * W, C_FLOATS = 17 * W;
   auto c_bias = [](int l) { return 9 * W + (l - 1) * W; };
-  __shared__ __attribute__((aligned(16))) float sm[C_FLOATS];
-  __shared__ __attribute__((aligned(16))) f32x4 xs[PTS];  // the workgroup's points
-  __shared__ __attribute__((aligned(16))) uint2 stk_lds[G::STK_BYTES / 8];
-  __shared__ __attribute__((aligned(16))) f32x4 red[NWV][PTS];  // per wave: f, grad x partials
+  static_assert(C_FLOATS * 4 == G::OFF_XS - G::OFF_SM, "small block size");
+  float* sm = reinterpret_cast<float*>(lds + G::OFF_SM);
+  f32x4* xs = reinterpret_cast<f32x4*>(lds + G::OFF_XS);  // the workgroup's points
+  uint2* stk_lds = reinterpret_cast<uint2*>(lds + G::OFF_STK);
+  auto& red = *reinterpret_cast<f32x4 (*)[NWV][PTS]>(lds + G::OFF_RED);  // per wave: f, grad x partials
 
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, col = lane & 15;
@@ -187,15 +201,15 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
     const int m0 = MTW * wave;
     return ((m0 >> 3) * NCT + ct) * G::FRAG + ((m0 & 7) / MTW) * 64 * PW + lane * PW;
   };
-  unsigned f8w[F8 ? NCT : 1][F8 ? MTW : 1];  // E4M3 words of the wave's M-tiles, per column tile
+  unsigned f8w[F8 ? NCT : 1][F8 ? MTW : 1] = {};  // E4M3 words of the wave's M-tiles, per column tile
   // The wave's rows cover whole K-blocks of the next contraction when MTW is
   // even: K-block kb0 + j holds local M-tiles 2j, 2j + 1 (see act_off).
   constexpr int NOWN = (SDF_K16_OWN && NS == 1 && !F8 && W != 512 && MTW % 2 == 0) ? MTW / 2 : 0;
   const int kb0 = wave * NOWN;
-  u32x4 ownB[NOWN > 0 ? NOWN : 1][NCT][NS];
+  u32x4 ownB[NOWN > 0 ? NOWN : 1][NCT][NS] = {};
 
   // first weight fragments (forward layer 2), in the wave's K-block order
-  AT Aq[R][MTW][NS];
+  AT Aq[R][MTW][NS] = {};
 #pragma unroll
   for (int s = 0; s < R - 1; ++s)
 #pragma unroll
@@ -206,8 +220,8 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
 
   // r_l of the wave's rows, l = LS+1..L-1, in registers: as the operand tuples
   // of the wave's own K-blocks (stq, NOWN > 0) or per M-tile (stk).
-  u32x4 stq[kLMax][NOWN > 0 ? NOWN : 1][NCT][NS];
-  uint2 stk[kLMax][MTW][NCT][NS];
+  u32x4 stq[kLMax][NOWN > 0 ? NOWN : 1][NCT][NS] = {};
+  uint2 stk[kLMax][MTW][NCT][NS] = {};
   auto stk_at = [&](int l, int mt, int ct, int ps) -> uint2& {
     return stk_lds[(((((l - 1) * NWV + wave) * MTW + mt) * NCT + ct) * NS + ps) * 64 + lane];
   };
@@ -622,7 +636,8 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile) {
 
 template <int W, int PREC, int MODE, int VAR>
 __global__ void K16_WG_SIZE(W) sdf_k16(const KArgs a) {
-  k16_tile<W, PREC, MODE, VAR>(a, blockIdx.x);
+  __shared__ __attribute__((aligned(16))) unsigned char lds[GeoP<W, PREC, VAR>::LDS_BYTES];
+  k16_tile<W, PREC, MODE, VAR>(a, blockIdx.x, lds, threadIdx.x);
 }
 
 // Several networks of one width in one launch: workgroup b runs tile
@@ -638,7 +653,74 @@ __global__ void K16_WG_SIZE(W) sdf_k16_group(const KArgs* __restrict__ nets,
     if (tile_start[mid] <= b) lo = mid; else hi = mid - 1;
   }
   const int i = __builtin_amdgcn_readfirstlane(lo);
-  k16_tile<W, PREC, MODE, VAR>(nets[i], b - tile_start[i]);
+  __shared__ __attribute__((aligned(16))) unsigned char lds[GeoP<W, PREC, VAR>::LDS_BYTES];
+  const KArgs a = nets[i];  // a private copy: loaded once, not again after every barrier
+  k16_tile<W, PREC, MODE, VAR>(a, b - tile_start[i], lds, threadIdx.x);
+}
+
+// Several networks of widths 128-512 (512-thread workgroups) in one
+// persistent launch: every workgroup takes work items -- one tile of one
+// network -- from the counter ctr[0] until none are left.  Network i owns
+// items item_start[i] .. item_start[i + 1] - 1 (its tiles in order); items
+// run network by network, so the workgroups in flight mostly share one
+// network's weights in L2.  The item table and the widths sit in LDS, the
+// current network's arguments too (copied when the network changes), and
+// each workgroup fetches its next item number while it works on the current
+// one, so nothing but LDS stands between two tiles.  The last workgroup to
+// run out of items sets both counters back to 0 for the next pass (ctr[1]
+// counts the workgroups that are done), so a pass needs no separate reset and
+// can be captured into a graph.
+constexpr int kPersistMaxNets = 512;
+template <int PREC>
+__global__ void K16_WG_SIZE(256) sdf_k16_persist(const KArgs* __restrict__ nets, const int* __restrict__ width,
+                                                 const int* __restrict__ item_start, int n_nets,
+                                                 int* __restrict__ ctr) {
+  constexpr int B128 = GeoP<128, PREC, 0>::LDS_BYTES, B256 = GeoP<256, PREC, 0>::LDS_BYTES,
+                B512 = GeoP<512, PREC, 0>::LDS_BYTES;
+  constexpr int BMAX = B128 > B256 ? (B128 > B512 ? B128 : B512) : (B256 > B512 ? B256 : B512);
+  __shared__ __attribute__((aligned(16))) unsigned char lds[BMAX];
+  __shared__ int tab[2 * kPersistMaxNets + 1];  // item_start[0..n_nets], then width[0..n_nets-1]
+  __shared__ int next_s;  // the next item number
+  for (int t = threadIdx.x; t <= n_nets; t += blockDim.x) {
+    tab[t] = item_start[t];
+    if (t < n_nets) tab[n_nets + 1 + t] = width[t];
+  }
+  if (threadIdx.x == 0) next_s = atomicAdd(&ctr[0], 1);
+  __syncthreads();
+  const int n_items = tab[n_nets];
+  for (;;) {
+    const int item = next_s;
+    if (item >= n_items) break;
+    int nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(&ctr[0], 1);  // used after this item
+    int lo = 0, hi = n_nets - 1;  // last i with item_start[i] <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tab[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    const int i = __builtin_amdgcn_readfirstlane(lo);
+    const KArgs& ka = nets[i];  // uniform address: read through the scalar cache
+    const int tile = item - tab[i];
+    // The thread index passes through an opaque move every item, so nothing
+    // derived from it is hoisted out of this loop: kept live across all three
+    // tile bodies, those values would not fit the registers.
+    int tid;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+    switch (__builtin_amdgcn_readfirstlane(tab[n_nets + 1 + i])) {
+      case 128: k16_tile<128, PREC, MODE_PROJECT, 0>(ka, tile, lds, tid); break;
+      case 256: k16_tile<256, PREC, MODE_PROJECT, 0>(ka, tile, lds, tid); break;
+      default: k16_tile<512, PREC, MODE_PROJECT, 0>(ka, tile, lds, tid); break;
+    }
+    if (threadIdx.x == 0) next_s = nxt;
+    __syncthreads();  // the next item is published; LDS is free for it
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();  // this workgroup's last fetch from ctr[0] comes first
+    if (atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+      atomicExch(&ctr[0], 0);
+      atomicExch(&ctr[1], 0);
+    }
+  }
 }
 
 #define SDF_K16_INST_V(W, PREC, MODE, VAR) \
@@ -647,8 +729,11 @@ __global__ void K16_WG_SIZE(W) sdf_k16_group(const KArgs* __restrict__ nets,
 #define SDF_K16_INST(W, PREC, MODE) SDF_K16_INST_V(W, PREC, MODE, 0)
 #define SDF_K16_MODES(W, PREC) \
   SDF_K16_INST(W, PREC, MODE_QUERY) SDF_K16_INST(W, PREC, MODE_GRAD) SDF_K16_INST(W, PREC, MODE_PROJECT)
-#define SDF_K16_PRECS(W) \
-  SDF_K16_MODES(W, PREC_BF16) SDF_K16_MODES(W, PREC_FP16) SDF_K16_MODES(W, PREC_BF16X3)
+
+#if defined(SDF_K16_PERSIST)
+template __global__ void sdf_k16_persist<SDF_K16_PREC>(const KArgs*, const int*, const int*, int, int*);
+#endif
+
 // The instantiations are split by hidden width and operand type so the build
 // can compile this file once per pair in parallel (-DSDF_K16_WIDTH=64..512,
 // -DSDF_K16_PREC=1..4, the PREC_* values); a macro left undefined selects every value.

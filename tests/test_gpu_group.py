@@ -80,6 +80,41 @@ def test_group_matches_single_calls_and_oracle(precision):
         n.close()
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_every_launch_mode_gives_the_same_bits(precision):
+    """Per-width, per-network and persistent passes run the same tile code on
+    the same tiles: two passes in a row agree bit for bit across modes (the
+    second pass also checks that the persistent counters were reset)."""
+    cs = small_set(n_nets=10, total=150_000)
+    cs.append({"spec": I.NetSpec((512,) * 4), "params": I.init_geometric(I.NetSpec((512,) * 4), 9),
+               "points": np.zeros((0, 3), np.float32)})
+    nets = [B.SdfNet(c["spec"], c["params"], precision) for c in cs]
+    X0 = [torch.from_numpy(np.ascontiguousarray(c["points"], np.float32)).cuda() for c in cs]
+    out = {}
+    for mode in ("per_network", "per_width", "persistent"):
+        X = [x.clone() for x in X0]
+        grp = B.SdfGroup(nets, X, EPS)
+        grp.set_launch(mode)
+        grp.collide_project()
+        grp.collide_project()
+        torch.cuda.synchronize()
+        out[mode] = X
+        grp.close()
+    for mode in ("per_width", "persistent"):
+        for i, (a, b) in enumerate(zip(out[mode], out["per_network"])):
+            assert torch.equal(a, b), "%s, net %d differs from per-network launches" % (mode, i)
+    if precision == "bf16":  # a member narrower than 128 has no persistent launch
+        spec = I.NetSpec((64,) * 3)
+        narrow = B.SdfNet(spec, I.init_geometric(spec, 2), precision)
+        grp = B.SdfGroup(nets[:1] + [narrow], [X0[0].clone(), X0[1].clone()], EPS)
+        with pytest.raises(B.SdfError):
+            grp.set_launch("persistent")
+        grp.close()
+        narrow.close()
+    for n in nets:
+        n.close()
+
+
 def test_group_rejects_bad_arguments():
     spec = I.NetSpec((128,) * 4)
     a = B.SdfNet(spec, I.init_geometric(spec, 1), "bf16")
@@ -96,7 +131,8 @@ def test_group_rejects_bad_arguments():
         n.close()
 
 
-def test_graph_of_thirty_passes_replays_exactly():
+@pytest.mark.parametrize("mode", ["per_network", "persistent"])
+def test_graph_of_thirty_passes_replays_exactly(mode):
     cs = small_set(n_nets=6, total=60_000)
     nets = [B.SdfNet(c["spec"], c["params"], "bf16") for c in cs]
     X0 = [torch.from_numpy(np.ascontiguousarray(c["points"], np.float32)).cuda() for c in cs]
@@ -109,6 +145,7 @@ def test_graph_of_thirty_passes_replays_exactly():
     # graph over static buffers
     Xs = [x.clone() for x in X0]
     gs = B.SdfGroup(nets, Xs, EPS)
+    gs.set_launch(mode)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):  # warm-up launch outside the capture

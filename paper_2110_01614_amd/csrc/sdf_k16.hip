@@ -23,17 +23,6 @@
 
 #include "sdf_device.hpp"
 
-#ifndef SDF_K16_D
-#define SDF_K16_D 1
-#endif
-
-#ifndef SDF_K16_SCHED
-#define SDF_K16_SCHED 1
-#endif
-#ifndef SDF_K16_OWN
-#define SDF_K16_OWN 1
-#endif
-
 namespace sdfc {
 
 // NS = 1: plain 16-bit operands.  NS = 2: every operand is carried as a BF16
@@ -49,7 +38,7 @@ struct GeoB {
   static constexpr int KM = F8 ? 128 : 32;      // K per MFMA
   static constexpr int KB = W / KM;            // K-blocks per layer
   static constexpr int FRAG = F8 ? 2 * kFrag : kFrag;  // bytes of one operand fragment
-  static constexpr int DMAX = (W == 512 ? (F8 ? 2 : 1) : (NS == 2 ? 2 : SDF_K16_D)) * (VAR == 1 ? 2 : 1);
+  static constexpr int DMAX = (W == 512 ? (F8 ? 2 : 1) : (NS == 2 ? 2 : 1)) * (VAR == 1 ? 2 : 1);
   static constexpr int D = KB < DMAX ? KB : DMAX;  // weight prefetch depth in K-steps
   // ring of weight fragments: step j uses slot j % R while step j + R - 1 is
   // loaded into its own slot; R divides KB so the slots line up across layers
@@ -58,18 +47,23 @@ struct GeoB {
   static_assert((R & (R - 1)) == 0, "ring size");
   // r_1..r_LS of the stack live in LDS (the reverse sweep reads them last);
   // the rest stay in registers.
-  static constexpr int LS = W == 256 ? 2 : (W > 256 ? 1 : 0);
+  static constexpr int LS = W == 256 ? 2 : (W > 256 ? (F8 ? 3 : 1) : 0);
   static constexpr int STK_BYTES = (LS > 0 ? LS : 1) * NWV * MTW * NCT * NS * 64 * 8;
   static constexpr int WAVE_BYTES = KB * MTW * NS * FRAG;  // one wave's slice of a layer
   static constexpr int LAYER_BYTES = NWV * WAVE_BYTES;
   static constexpr int ACT_BYTES = KB * NCT * FRAG;        // one exchange buffer part
   static constexpr int NS_ = NS;
+  // The biases of layers 1..8 sit in LDS with the rest of the small block,
+  // except for FP8 at width 512, whose LDS holds three layers of the stack
+  // instead: there each wave reads its biases from L2 once per layer.
+  static constexpr bool SM_BIAS = !(W == 512 && F8);
+  static constexpr int SM_FLOATS = (SM_BIAS ? 17 : 9) * W;
   // LDS of one workgroup (byte offsets, 16-byte aligned): the double-buffered
   // exchange buffers, the small FP32 block (17 W floats), the points, the
   // LDS part of the reverse-sweep stack, the per-wave partial sums.
   static constexpr int OFF_ACT = 0;
   static constexpr int OFF_SM = OFF_ACT + 2 * NS * ACT_BYTES;
-  static constexpr int OFF_XS = OFF_SM + 17 * W * 4;
+  static constexpr int OFF_XS = OFF_SM + SM_FLOATS * 4;
   static constexpr int OFF_STK = OFF_XS + PTS * 16;
   static constexpr int OFF_RED = OFF_STK + STK_BYTES;
   static constexpr int LDS_BYTES = OFF_RED + NWV * PTS * 16;
@@ -136,7 +130,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
   // skf: 4W | wof: W | bias of layers 1..8: 8W]; the gradient copies of l1 and
   // skf and the reverse seed are these times per-network scalars (a.c_l1g,
   // a.c_skg, a.c_wob).  Layer 1's bias slot holds the Fourier net's bias.
-  constexpr int C_L1 = 0, C_SKF = 4 * W, C_WOF = 8 * W, C_FLOATS = 17 * W;
+  constexpr int C_L1 = 0, C_SKF = 4 * W, C_WOF = 8 * W, C_FLOATS = G::SM_FLOATS;
   auto c_bias = [](int l) { return 9 * W + (l - 1) * W; };
   static_assert(C_FLOATS * 4 == G::OFF_XS - G::OFF_SM, "small block size");
   float* sm = reinterpret_cast<float*>(lds + G::OFF_SM);
@@ -176,9 +170,10 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
     }
     for (int i = tid; i < W / 4; i += NT) {  // wof, layer-1 bias (Fourier), biases 2..8
       dst[C_WOF / 4 + i] = src[SL.wof() / 4 + i];
-      dst[c_bias(1) / 4 + i] = src[SL.l1g() / 4 + i];
+      if constexpr (G::SM_BIAS) dst[c_bias(1) / 4 + i] = src[SL.l1g() / 4 + i];
     }
-    for (int i = tid; i < (kLMax - 1) * W / 4; i += NT) dst[c_bias(2) / 4 + i] = src[SL.bias(2) / 4 + i];
+    if constexpr (G::SM_BIAS)
+      for (int i = tid; i < (kLMax - 1) * W / 4; i += NT) dst[c_bias(2) / 4 + i] = src[SL.bias(2) / 4 + i];
   }
 
 
@@ -204,7 +199,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
   unsigned f8w[F8 ? NCT : 1][F8 ? MTW : 1] = {};  // E4M3 words of the wave's M-tiles, per column tile
   // The wave's rows cover whole K-blocks of the next contraction when MTW is
   // even: K-block kb0 + j holds local M-tiles 2j, 2j + 1 (see act_off).
-  constexpr int NOWN = (SDF_K16_OWN && NS == 1 && !F8 && W != 512 && MTW % 2 == 0) ? MTW / 2 : 0;
+  constexpr int NOWN = (NS == 1 && !F8 && W != 512 && MTW % 2 == 0) ? MTW / 2 : 0;
   const int kb0 = wave * NOWN;
   u32x4 ownB[NOWN > 0 ? NOWN : 1][NCT][NS] = {};
 
@@ -425,7 +420,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
     for (int j = NOWN; j < KB; ++j) {
       prefetchA(j);
       if (j + 1 < KB) loadB(Bv[(j + 1 - NOWN) & 1], j + 1);
-      if constexpr (SDF_K16_SCHED) __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_sched_barrier(0);
       step(j, Bv[(j - NOWN) & 1]);
     }
   };
@@ -444,7 +439,12 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
     f32x4 acc[MTW][NCT];
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
-      const f32x4 b = *reinterpret_cast<const f32x4*>(&sm[c_bias(l) + 16 * (MTW * wave + mt) + 4 * g]);
+      const int fo = 16 * (MTW * wave + mt) + 4 * g;
+      f32x4 b;
+      if constexpr (G::SM_BIAS)
+        b = *reinterpret_cast<const f32x4*>(&sm[c_bias(l) + fo]);
+      else
+        b = *reinterpret_cast<const f32x4*>(a.small + (l == 1 ? SL.l1g() : SL.bias(l)) + fo);
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[mt][ct] = b;
     }

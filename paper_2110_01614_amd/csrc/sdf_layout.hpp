@@ -50,17 +50,14 @@ struct SmallLayout {
 // stream is ordered by wave), the launcher and the kernel.  NS = 1: plain
 // 16-bit operands; NS = 2: BF16 hi/lo pairs; f8: E4M3 operands (wider
 // weight fragments).  Widths from 128 run 8 waves (2 per SIMD) on 64 points;
-// pairs, FP8 and width 512 take fewer points so that the reverse-sweep stack
-// and the operands of a wave still fit its registers.
+// pairs (32; 16 at width 512) and width 512 (32) take fewer points so that
+// the reverse-sweep stack and the operands of a wave still fit its registers.
 __host__ __device__ constexpr int k16_waves(int W) { return W >= 128 ? 8 : 4; }
-#ifndef SDF_K16_COLS256
-#define SDF_K16_COLS256 4
-#endif
 // Tile variant 1 (plain 16-bit collide_project at widths 128-512, picked by
 // the autotuner): half the points of variant 0 and twice its weight-prefetch
 // depth.
 __host__ __device__ constexpr int k16_cols(int W, int NS, bool f8 = false, int var = 0) {
-  const int c = W == 512 ? ((NS == 1 && !f8) ? 2 : 1) : (NS == 1 ? (W == 256 ? SDF_K16_COLS256 : 4) : 2);
+  const int c = W == 512 ? (NS == 1 ? 2 : 1) : (NS == 1 ? 4 : 2);
   return var == 1 && c > 1 ? c / 2 : c;
 }
 __host__ __device__ constexpr int k16_points(int W, int NS, bool f8 = false, int var = 0) {

@@ -101,41 +101,43 @@ def traffic_record(copy_fetch, copy_write, k_fetch, k_write, kernel, precision, 
     print(json.dumps(rec))
 
 
-def pmc_summary(root, precisions, n_points=1_000_000, flops_per_pt=1842176, clock_ghz=2.4):
-    """Markdown summary of rocprofv3 counter passes of the cloth1m kernel.
+def pmc_summary(root, precisions, n_points=1_000_000, flops_per_pt=1842176, width=256, shared=None, skip=5):
+    """Markdown summary of rocprofv3 counter passes of the collide_project kernels.
 
     root/<prec>/p1..p3: SQ / TCC / TCP counter passes (--pmc), root/<prec>/kt:
-    --kernel-trace --stats.  Values are per dispatch (mean over the
-    dispatches of the width-256 collide_project kernel)."""
+    --kernel-trace --stats (shared = one directory holding the passes of every
+    precision instead, as a run of the width-512 study gives).  Values are per
+    dispatch (mean over the dispatches of the collide_project kernel of the
+    given width); the trace drops the first `skip` dispatches (warm-up; FP32: 2)."""
     import csv
     import glob
 
-    def counters(prec, i, name):
+    def counters(d, i, name):
         vals = {}
-        for f in glob.glob(os.path.join(root, prec, "p%d" % i, "*counter_collection.csv")):
+        for f in glob.glob(os.path.join(root, d, "p%d" % i, "*counter_collection.csv")):
             for r in csv.DictReader(open(f)):
                 if name in r["Kernel_Name"]:
                     vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
         return {k: float(np.mean(v)) for k, v in vals.items()}
 
-    def trace(prec, name):
-        """(timed launches, mean ms, median ms): the kernel's dispatches in the
-        trace after the benchmark's warm-up launches (5; FP32: 2)."""
-        for f in glob.glob(os.path.join(root, prec, "kt", "*kernel_trace.csv")):
-            d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in csv.DictReader(open(f))
+    def trace(d, name, skip):
+        """(timed launches, mean ms, median ms) of the kernel's dispatches."""
+        for f in glob.glob(os.path.join(root, d, "kt", "*kernel_trace.csv")):
+            t = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in csv.DictReader(open(f))
                  if name in r["Kernel_Name"]]
-            d = d[2 if prec == "fp32" else 5:]
-            if d:
-                return len(d), float(np.mean(d)), float(np.median(d))
+            t = t[skip:]
+            if t:
+                return len(t), float(np.mean(t)), float(np.median(t))
         return None
 
     rows = []
     for prec in precisions:
-        name = K16_NAME % PREC_ID[prec] if prec in PREC_ID else "sdf_k32<256, 2>"
+        name = ("sdf_k16<%d, %d, 2, 0>" % (width, PREC_ID[prec])) if prec in PREC_ID else "sdf_k32<%d, 2>" % width
+        d = shared or prec
         c = {}
         for i in (1, 2, 3):
-            c.update(counters(prec, i, name))
-        kt = trace(prec, name)
+            c.update(counters(d, i, name))
+        kt = trace(d, name, 2 if prec == "fp32" else skip)
         if not c or kt is None:
             continue
         xcd_cycles = c["GRBM_GUI_ACTIVE"] / 8.0  # summed over the 8 XCDs
@@ -153,16 +155,18 @@ def pmc_summary(root, precisions, n_points=1_000_000, flops_per_pt=1842176, cloc
             "wait": c["SQ_WAIT_INST_ANY"] / c["SQ_WAVE_CYCLES"],
             "lds_conflict": c["SQ_LDS_BANK_CONFLICT"], "lds_insts": c["SQ_INSTS_LDS"],
             "l2_hit": c["TCC_HIT"] / max(c["TCC_REQ"], 1.0), "l2cu_gb": l2cu / 1e9,
-            "l2cu_tbs": l2cu / (kt[1] * 1e-3) / 1e12})
+            "l2cu_tbs": l2cu / (kt[1] * 1e-3) / 1e12,
+            "l2_miss_gb": c.get("TCC_EA0_RDREQ", 0.0) * 128 / 1e9})
     out = ["| operands | kernel | launches | mean ms (trace) | median ms | algorithmic TFLOP/s | issued MFMA TFLOP | "
            "MFMA busy | MFMA+VALU co-issue | non-MFMA VALU insts | trans insts | wait fraction | "
-           "LDS bank-conflict cycles | L2 hit | L2->CU GB | L2->CU TB/s |", "|" + "---|" * 16]
+           "LDS bank-conflict cycles | L2 hit | L2->CU GB | L2->CU TB/s | L2 read misses GB |", "|" + "---|" * 17]
     for r in rows:
         out.append("| %s | `%s` | %d | %.3f | %.3f | %.0f | %.3f | %.1f %% | %.1f %% | %.3g | %.3g | %.0f %% | %.3g | "
-                   "%.2f %% | %.1f | %.1f |" % (
+                   "%.2f %% | %.1f | %.1f | %.1f |" % (
                        r["prec"], r["kernel"], r["calls"], r["ms"], r["median_ms"], r["algo_tflops"],
                        r["issued_tflop"], 100 * r["mfma_busy"], 100 * r["coexec"], r["valu_per_tile_wave"], r["trans"],
-                       100 * r["wait"], r["lds_conflict"], 100 * r["l2_hit"], r["l2cu_gb"], r["l2cu_tbs"]))
+                       100 * r["wait"], r["lds_conflict"], 100 * r["l2_hit"], r["l2cu_gb"], r["l2cu_tbs"],
+                       r["l2_miss_gb"]))
     print("\n".join(out))
     return rows
 
@@ -439,6 +443,10 @@ def main():
         return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary, ["bf16", "fp16", "bf16x3", "fp8", "fp32"])
+        if os.path.isdir(os.path.join(args.pmc_summary, "wide")):  # the width-512 study: 4M points
+            print()
+            pmc_summary(args.pmc_summary, ["bf16", "bf16x3", "fp8"], n_points=4_000_000, flops_per_pt=7354368,
+                        width=512, shared="wide", skip=2)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the collision path shards across GPUs with no exchange "

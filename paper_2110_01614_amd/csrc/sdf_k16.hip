@@ -38,7 +38,8 @@ struct GeoB {
   static constexpr int KM = F8 ? 128 : 32;      // K per MFMA
   static constexpr int KB = W / KM;            // K-blocks per layer
   static constexpr int FRAG = F8 ? 2 * kFrag : kFrag;  // bytes of one operand fragment
-  static constexpr int DMAX = (W == 512 ? (F8 ? 2 : 1) : (NS == 2 ? 2 : 1)) * (VAR == 1 ? 2 : 1);
+  // (pairs: 3, a four-slot ring, the weights three K-steps ahead)
+  static constexpr int DMAX = (W == 512 ? (F8 ? 2 : 1) : (NS == 2 ? 3 : 1)) * (VAR == 1 ? 2 : 1);
   static constexpr int D = KB < DMAX ? KB : DMAX;  // weight prefetch depth in K-steps
   // ring of weight fragments: step j uses slot j % R while step j + R - 1 is
   // loaded into its own slot; R divides KB so the slots line up across layers

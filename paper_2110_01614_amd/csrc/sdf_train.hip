@@ -130,49 +130,94 @@ __device__ __forceinline__ int64_t wgrad_dst(const TrainNet& t, int l, int j, in
 // (l = L+1): E = dLoss/df [n][16] (row 0), H = H_L.  Columns map to dW_l
 // (hidden and skip x-columns), db_l (the "1" column), dw_o and db_o.
 // Workgroup b takes item b % items and point slice b / items of nsplit
-// equal slices.  nsplit == 1: grad += the sum directly (one owner per
-// element); otherwise the block is written to part[slice][item][64][64] and
-// wgrad_reduce_kernel adds the slices in a fixed order.
+// slices of whole 64-point tiles.  Each tile of the block's E rows and H
+// columns is staged in LDS with 16-byte loads (read from global once per
+// workgroup, the next tile's loads in flight while the current one is
+// contracted); wave w contracts rows 16w..16w+15 of the block against its
+// up to 64 columns on v_mfma_f32_16x16x4_f32.  nsplit == 1: grad += the sum
+// directly (one owner per element); otherwise the block is written to
+// part[slice][item][64][64] and wgrad_reduce_kernel adds the slices in a
+// fixed order.
+constexpr int kWgP = 64;  // points per staged tile
+constexpr int kWgS = 80;  // LDS row stride in floats: the four point rows read by one MFMA start 16 banks apart
 __global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __restrict__ E,
                                                     const float* __restrict__ H,
                                                     const float* __restrict__ U, int64_t n, int items,
                                                     int nsplit, float* __restrict__ part,
                                                     float* __restrict__ grad) {
+  __shared__ __attribute__((aligned(16))) float sE[2][kWgP * kWgS];
+  __shared__ __attribute__((aligned(16))) float sH[2][kWgP * kWgS];
   const int W = t.W, L = t.L;
   const int item = blockIdx.x % items, slice = blockIdx.x / items;
   const WItem wi = wgrad_item(t, item);
   const int l = wi.l, CB = W / 64 + 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const bool out_layer = (l == L + 1);
   const bool tail = (wi.cb == CB - 1);
   const int ncb = tail ? 1 : 4;  // N-tiles of 16 in this block
   const int col0 = tail ? W : 64 * wi.cb;
-  // rows of this wave: 16 per wave (the output layer has one real row: wave 0)
-  if (out_layer && wave > 0) return;
-  const int row0 = 64 * wi.rb + 16 * wave;
   const float* Eb = out_layer ? U : E + (size_t)(l - 1) * n * W;
   const int es = out_layer ? 16 : W;
+  const int er0 = out_layer ? 0 : 64 * wi.rb;  // first staged E column
+  const int ew4 = out_layer ? 4 : 16;          // staged E columns / 4
   const float* Hb = H + (size_t)(l - 1) * n * (W + 16);
   const int hs = W + 16;
-  // this slice's points, in steps of 4 (one MFMA K-step)
-  const int64_t steps = (n + 3) / 4;
-  const int64_t p_lo = 4 * (steps * slice / nsplit), p_hi = 4 * (steps * (slice + 1) / nsplit);
-  f32x4 acc[4] = {};
-#pragma unroll 4
-  for (int64_t p0 = p_lo; p0 < p_hi; p0 += 4) {
-    const int64_t p = p0 + g;
-    const bool ok = p < n;
-    const float a = ok ? Eb[p * es + (out_layer ? c16 : row0 + c16)] : 0.0f;
+  const int hw4 = 4 * ncb;                     // staged H columns / 4
+  // the output layer has one real row: only wave 0 contracts (all waves stage)
+  const bool active = !(out_layer && wave > 0);
+  const int64_t tiles = (n + kWgP - 1) / kWgP;
+  const int64_t t_lo = tiles * slice / nsplit, t_hi = tiles * (slice + 1) / nsplit;
+  const int nE = ew4 * kWgP / 256, nH = hw4 * kWgP / 256;  // float4 loads per thread: 4 or 1
+  float4 rE[4], rH[4];
+  auto load = [&](int64_t tile) {
+    const int64_t p0 = tile * kWgP;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      if (nt < ncb) {
-        const float b = ok ? Hb[p * hs + col0 + 16 * nt + c16] : 0.0f;
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[nt], 0, 0, 0);
+    for (int i = 0; i < 4; ++i) {
+      const int q = tid + 256 * i;
+      if (i < nE) {
+        const int64_t p = p0 + q / ew4;
+        rE[i] = p < n ? *reinterpret_cast<const float4*>(Eb + p * es + er0 + 4 * (q % ew4))
+                      : float4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+      if (i < nH) {
+        const int64_t p = p0 + q / hw4;
+        rH[i] = p < n ? *reinterpret_cast<const float4*>(Hb + p * hs + col0 + 4 * (q % hw4))
+                      : float4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = tid + 256 * i;
+      if (i < nE) *reinterpret_cast<float4*>(&sE[buf][(q / ew4) * kWgS + 4 * (q % ew4)]) = rE[i];
+      if (i < nH) *reinterpret_cast<float4*>(&sH[buf][(q / hw4) * kWgS + 4 * (q % hw4)]) = rH[i];
+    }
+  };
+  f32x4 acc[4] = {};
+  const int erow = out_layer ? c16 : 16 * wave + c16;  // this lane's E column in the staged tile
+  if (t_lo < t_hi) load(t_lo);
+  for (int64_t tt = t_lo; tt < t_hi; ++tt) {
+    const int buf = (int)((tt - t_lo) & 1);
+    store(buf);  // buffer buf was last read two tiles ago, before the previous barrier
+    __syncthreads();
+    if (tt + 1 < t_hi) load(tt + 1);
+    if (active) {
+      const float* e = sE[buf];
+      const float* h = sH[buf];
+#pragma unroll
+      for (int k = 0; k < kWgP; k += 4) {
+        const float a = e[(k + g) * kWgS + erow];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+          if (nt < ncb) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, h[(k + g) * kWgS + 16 * nt + c16], acc[nt], 0, 0, 0);
       }
     }
   }
+  if (!active) return;
   // acc[nt][i] = sum_p E[p][row0 + 4g + i] H[p][col0 + 16 nt + c16]
+  const int row0 = 64 * wi.rb + 16 * wave;
   for (int nt = 0; nt < ncb; ++nt) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {

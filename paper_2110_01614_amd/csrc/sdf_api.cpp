@@ -820,7 +820,7 @@ int train_run(const sdf_net_desc* desc, int W, int L, int skip, const float* par
     if (nsplit > 1)
       hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((items * 4096 + 255) / 256), dim3(256), 0, s, t, part, items,
                          nsplit, grad_params);
-    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, s, a.ws_loss, cn, loss);
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, s, a.ws_loss, cn, loss);
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? SDF_OK : hip_fail(e, "kernel launch");

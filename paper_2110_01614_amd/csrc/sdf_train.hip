@@ -73,15 +73,24 @@ __global__ void __launch_bounds__(256) fill_kernel(float* __restrict__ p, int64_
     p[i] = v;
 }
 
-// loss += sum of the chunk's per-point terms, one workgroup, fixed order.
-__global__ void __launch_bounds__(256) loss_reduce_kernel(const float* __restrict__ terms, int64_t n,
-                                                          float* __restrict__ loss) {
-  __shared__ float part[256];
-  float s = 0.0f;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += terms[i];
-  part[threadIdx.x] = s;
+// loss += sum of the chunk's per-point terms: one workgroup of 1024
+// threads, four independent partial sums per thread (so four loads are in
+// flight), then a tree over the threads; the order is fixed.
+constexpr int kLossThreads = 1024;
+__global__ void __launch_bounds__(kLossThreads) loss_reduce_kernel(const float* __restrict__ terms, int64_t n,
+                                                                   float* __restrict__ loss) {
+  __shared__ float part[kLossThreads];
+  float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t i = threadIdx.x; i < n; i += 4 * kLossThreads) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t j = i + (int64_t)u * kLossThreads;
+      if (j < n) s[u] += terms[j];
+    }
+  }
+  part[threadIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kLossThreads / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
     __syncthreads();
   }
@@ -130,7 +139,7 @@ __device__ __forceinline__ int64_t wgrad_dst(const TrainNet& t, int l, int j, in
 // (l = L+1): E = dLoss/df [n][16] (row 0), H = H_L.  Columns map to dW_l
 // (hidden and skip x-columns), db_l (the "1" column), dw_o and db_o.
 // Workgroup b takes item b % items and point slice b / items of nsplit
-// slices of whole 64-point tiles.  Each tile of the block's E rows and H
+// slices of whole 16-point tiles.  Each tile of the block's E rows and H
 // columns is staged in LDS with 16-byte loads (read from global once per
 // workgroup, the next tile's loads in flight while the current one is
 // contracted); wave w contracts rows 16w..16w+15 of the block against its
@@ -138,7 +147,7 @@ __device__ __forceinline__ int64_t wgrad_dst(const TrainNet& t, int l, int j, in
 // directly (one owner per element); otherwise the block is written to
 // part[slice][item][64][64] and wgrad_reduce_kernel adds the slices in a
 // fixed order.
-constexpr int kWgP = 64;  // points per staged tile
+constexpr int kWgP = 16;  // points per staged tile (small tiles: four workgroups per CU)
 constexpr int kWgS = 80;  // LDS row stride in floats: the four point rows read by one MFMA start 16 banks apart
 __global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __restrict__ E,
                                                     const float* __restrict__ H,
@@ -168,19 +177,19 @@ __global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __r
   const bool active = !(out_layer && wave > 0);
   const int64_t tiles = (n + kWgP - 1) / kWgP;
   const int64_t t_lo = tiles * slice / nsplit, t_hi = tiles * (slice + 1) / nsplit;
-  const int nE = ew4 * kWgP / 256, nH = hw4 * kWgP / 256;  // float4 loads per thread: 4 or 1
-  float4 rE[4], rH[4];
+  const int qE = ew4 * kWgP, qH = hw4 * kWgP;  // float4s of a staged tile
+  float4 rE[kWgP / 16], rH[kWgP / 16];  // up to 64 x kWgP floats of each per 256 threads
   auto load = [&](int64_t tile) {
     const int64_t p0 = tile * kWgP;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kWgP / 16; ++i) {
       const int q = tid + 256 * i;
-      if (i < nE) {
+      if (q < qE) {
         const int64_t p = p0 + q / ew4;
         rE[i] = p < n ? *reinterpret_cast<const float4*>(Eb + p * es + er0 + 4 * (q % ew4))
                       : float4{0.0f, 0.0f, 0.0f, 0.0f};
       }
-      if (i < nH) {
+      if (q < qH) {
         const int64_t p = p0 + q / hw4;
         rH[i] = p < n ? *reinterpret_cast<const float4*>(Hb + p * hs + col0 + 4 * (q % hw4))
                       : float4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -189,10 +198,10 @@ __global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __r
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kWgP / 16; ++i) {
       const int q = tid + 256 * i;
-      if (i < nE) *reinterpret_cast<float4*>(&sE[buf][(q / ew4) * kWgS + 4 * (q % ew4)]) = rE[i];
-      if (i < nH) *reinterpret_cast<float4*>(&sH[buf][(q / hw4) * kWgS + 4 * (q % hw4)]) = rH[i];
+      if (q < qE) *reinterpret_cast<float4*>(&sE[buf][(q / ew4) * kWgS + 4 * (q % ew4)]) = rE[i];
+      if (q < qH) *reinterpret_cast<float4*>(&sH[buf][(q / hw4) * kWgS + 4 * (q % hw4)]) = rH[i];
     }
   };
   f32x4 acc[4] = {};

@@ -449,9 +449,11 @@ int orc_fit_loss(int L, const int* widths, int skip, double beta, const double* 
   const int nt = nthreads();
   double* pool = (double*)malloc(sizeof(double) * per * (size_t)nt);
   double* gpool = (double*)calloc((size_t)np * (size_t)nt, sizeof(double));
-  if (!pool || !gpool) {
+  double* lpool = (double*)calloc((size_t)nt, sizeof(double));
+  if (!pool || !gpool || !lpool) {
     free(pool);
     free(gpool);
+    free(lpool);
     return -2;
   }
 #pragma omp parallel
@@ -507,15 +509,17 @@ int orc_fit_loss(int L, const int* widths, int skip, double beta, const double* 
           }
         }
       }
-#pragma omp critical
-      total += part;
+      lpool[thread_id()] = part;
     }
   }
-  /* fixed-order reduction of the per-thread gradients */
-  for (int t = 0; t < nt; ++t)
+  /* fixed-order reduction of the per-thread losses and gradients */
+  for (int t = 0; t < nt; ++t) {
+    total += lpool[t];
     for (int64_t k = 0; k < np; ++k) grad[k] += gpool[(size_t)np * t + k];
+  }
   free(pool);
   free(gpool);
+  free(lpool);
   if (loss) *loss = total / (double)(npts > 0 ? npts : 1);
   return 0;
 }

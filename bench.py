@@ -312,34 +312,53 @@ def fitting(torch, B, I, steps, warmup=2, n=1_000_000):
             "tflops": flops / (ms * 1e-3) / 1e12, "fp32_mfma_frac": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"]}
 
 
-def precision_study(torch, B, I, steps):
-    """3->512x8->1 skip 5 on 4M uniform points (geometric init): BF16, BF16x3
-    and FP8 operands, time per collide_project pass and error against FP64."""
+def precision_study(torch, B, I, steps, n_acc=65536):
+    """3->512x8->1 skip 5 on 4M uniform points: BF16, BF16x3 and FP8 operands,
+    time per collide_project pass (geometric init) and error against FP64 on
+    n_acc sampled points for the geometric and the N(0, 0.02) initialisation
+    (the FP64 references are computed once per initialisation)."""
+    import oracle
     spec, params, pts, eps = I.workload_inputs("wide4m")
+    pn = I.workload_inputs("wide4m", n=1, init="normal")[1]
     n = len(pts)
     fpp = flops_per_point(spec)
     X0 = torch.from_numpy(pts).cuda()
-    out = {"workload": "wide4m: 3->512x8->1, skip 5, geometric init seed 0, %d uniform points seed 1" % n,
-           "flops_per_point": fpp}
+    idx = np.random.default_rng(3).choice(n, n_acc, replace=False)
+    sample = np.ascontiguousarray(pts[idx])
+    refs = {init: oracle.collide_project(spec, prm, sample, eps) for init, prm in
+            (("geometric", params), ("normal", pn))}
+    out = {"workload": "wide4m: 3->512x8->1, skip 5, geometric init seed 0 (timed; also N(0, 0.02) seed 0 for "
+                       "the errors), %d uniform points seed 1" % n,
+           "flops_per_point": fpp, "accuracy_sample": n_acc}
     for prec in ("bf16", "bf16x3", "fp8"):
         net = B.SdfNet(spec, params, prec)
         X = X0.clone()
         wall, per = time_steps(net, X, eps, steps, 2, torch)
         ms = float(np.mean(per))
         tf = fpp * n / (ms * 1e-3) / 1e12
+        netn = B.SdfNet(spec, pn, prec)
         out[prec] = {"kernel_ms_mean": ms, "points_per_s": n / (ms * 1e-3), "tflops": tf,
                      "mfma_frac": tf / PEAK_TFLOPS[prec],
-                     "accuracy_vs_fp64": accuracy(spec, params, pts, net, torch, n=1024)}
+                     "accuracy_vs_fp64": accuracy(spec, params, pts, net, torch, sample=sample,
+                                                  ref=refs["geometric"]),
+                     "accuracy_vs_fp64_normal_init": accuracy(spec, pn, pts, netn, torch, sample=sample,
+                                                              ref=refs["normal"])}
         net.close()
+        netn.close()
         del X
     return out
 
 
-def accuracy(spec, params, pts, net, torch, n=4096, eps=0.005):
+def accuracy(spec, params, pts, net, torch, n=4096, eps=0.005, sample=None, ref=None):
+    """SDF and normal-angle errors of net against FP64 on n sampled points
+    (or on `sample` with its oracle result `ref`)."""
     import oracle
-    idx = np.random.default_rng(3).choice(len(pts), n, replace=False)
-    ref = oracle.collide_project(spec, params, pts[idx], eps)
-    X = torch.from_numpy(pts[idx]).cuda()
+    if sample is None:
+        idx = np.random.default_rng(3).choice(len(pts), n, replace=False)
+        sample = pts[idx]
+    if ref is None:
+        ref = oracle.collide_project(spec, params, sample, eps)
+    X = torch.from_numpy(np.ascontiguousarray(sample)).cuda()
     f, g = net.query_grad(X)
     torch.cuda.synchronize()
     f, g = f.cpu().numpy(), g.cpu().numpy().astype(np.float64)
@@ -348,7 +367,7 @@ def accuracy(spec, params, pts, net, torch, n=4096, eps=0.005):
     ang = np.arctan2(cr, np.einsum("ij,ij->i", g, ref["grad"]))
     return {"sdf_max": float(ferr.max()), "sdf_p99": float(np.quantile(ferr, 0.99)),
             "angle_max_rad": float(ang.max()), "angle_p99_rad": float(np.quantile(ang, 0.99)),
-            "sample": n}
+            "sample": len(sample)}
 
 
 def _oracle_threads(k):

@@ -46,7 +46,7 @@ extern "C" {
 enum {
   SDF_OK = 0,
   SDF_EINVAL = -1,       /* bad argument (null pointer, n < 0, non-finite eps, ...) */
-  SDF_EUNSUPPORTED = -2, /* a network shape or precision this build has no kernel for */
+  SDF_EUNSUPPORTED = -2, /* a network shape or precision the library has no kernel for */
   SDF_ENOMEM = -3,       /* device allocation failed in sdf_net_create */
   SDF_EDEVICE = -4       /* a HIP runtime call or launch failed */
 };
@@ -75,7 +75,7 @@ enum { SDF_FP32 = 0, SDF_BF16 = 1, SDF_FP16 = 2, SDF_BF16X3 = 3, SDF_FP8 = 4 };
  * gamma(x) = [sin(2 pi B x), cos(2 pi B x)] (B an m x 3 matrix, fixed), layer 1
  * has K = 2m inputs and there is no skip input (skip_layer must be 0); this
  * build requires 2m == width and BF16, FP16 or BF16X3 operands.
- * This build has kernels for equal hidden widths of 64, 128, 256 or 512 (512:
+ * The library has kernels for equal hidden widths of 64, 128, 256 or 512 (512:
  * 16-bit and FP8 precisions only; FP8: 128 and up), depth 2..8, skip 0 or
  * 2..depth; other shapes return SDF_EUNSUPPORTED. */
 typedef struct {

@@ -1,7 +1,7 @@
 """The FP64 oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
 (gcc, host code only) and driven through every entry point, including its
 error paths and degenerate inputs.  Any out-of-bounds access, leak, signed
-overflow or other undefined behaviour aborts the driver."""
+overflow or other undefined behaviour aborts the test program."""
 import os
 import shutil
 import subprocess

@@ -168,7 +168,7 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts,
  *                       of decreasing cost per tile, until none are left (needs
  *                       every member of width 128 or more, 512 members at
  *                       most).
- * A new group uses SDF_GROUP_PER_NETWORK.  Every mode computes the same bits
+ * A new group uses SDF_GROUP_PER_WIDTH.  Every mode computes the same bits
  * per vertex. */
 enum { SDF_GROUP_PER_WIDTH = 0, SDF_GROUP_PER_NETWORK = 1, SDF_GROUP_PERSISTENT = 2 };
 

@@ -920,7 +920,7 @@ int sdf_train_step_noalloc(const sdf_net_desc* desc, const float* params, const 
 struct sdf_group {
   int device = 0;
   int prec = 0;
-  int mode = SDF_GROUP_PER_NETWORK;  // SDF_GROUP_*: how a pass is launched
+  int mode = SDF_GROUP_PER_WIDTH;  // SDF_GROUP_*: how a pass is launched
   // persistent launch (all members of width >= 128, at most 512 of them):
   // members in work order, their widths, their first work items (n + 1), the
   // two work counters; one workgroup per CU
@@ -1184,7 +1184,7 @@ int sdf_group_create(const sdf_net* const* nets, int n_nets, float* const* pts, 
     grp->d_ctr = (int*)(m + o_ctr);
     grp->n_persist = nm;
     grp->persist_ok = persist_ok;
-    grp->mode = SDF_GROUP_PER_NETWORK;
+    grp->mode = SDF_GROUP_PER_WIDTH;
   }
   (void)hipSetDevice(prev);
   *out = grp;

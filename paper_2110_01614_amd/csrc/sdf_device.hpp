@@ -71,6 +71,30 @@ struct TrainNet {
   __host__ __device__ int K(int l) const { return (l == 1 ? 3 : W) + (l == skip ? 3 : 0); }
 };
 
+// Global-memory views of a pointer.  Loads and stores through them are
+// global_load / global_store rather than flat ones.  The compiler infers the
+// address space of pointers that arrive as kernel arguments, but not of
+// pointers read from a table in memory (the grouped kernels); flat loads
+// also count against the LDS wait counter, so every wait for an LDS read
+// would wait for the weight loads in flight as well.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
+// gmem(p) where GV, else p itself (kernels whose pointers are kernel
+// arguments keep the compiler's own addressing).
+template <bool GV, class T>
+__device__ __forceinline__ auto gview(T* p) {
+  if constexpr (GV)
+    return gmem(p);
+  else
+    return p;
+}
+
 __device__ __forceinline__ unsigned lds_u32(const void* p) {
   return (unsigned)(uintptr_t)(__attribute__((address_space(3))) const void*)p;
 }
@@ -198,7 +222,7 @@ __device__ __forceinline__ void to_local(const KArgs& a, float& x0, float& x1, f
 // 0 (lanes 0..15) store; the other groups hold the same reduced values.
 // x0..x2: the vertex as loaded (world frame).  g0..g2: gradient in the
 // network's frame.
-template <int MODE>
+template <int MODE, bool GV = false>
 __device__ __forceinline__ void store_outputs(const KArgs& a, int64_t p, bool store, float f,
                                               float g0, float g1, float g2, float x0, float x1,
                                               float x2) {
@@ -212,12 +236,12 @@ __device__ __forceinline__ void store_outputs(const KArgs& a, int64_t p, bool st
     g2 = h2;
   }
   if constexpr (MODE == MODE_QUERY) {
-    a.sdf[p] = f;
+    gview<GV>(a.sdf)[p] = f;
   } else if constexpr (MODE == MODE_GRAD) {
-    if (a.sdf) a.sdf[p] = f;
-    a.grad[3 * p] = g0;
-    a.grad[3 * p + 1] = g1;
-    a.grad[3 * p + 2] = g2;
+    if (a.sdf) gview<GV>(a.sdf)[p] = f;
+    gview<GV>(a.grad)[3 * p] = g0;
+    gview<GV>(a.grad)[3 * p + 1] = g1;
+    gview<GV>(a.grad)[3 * p + 2] = g2;
   } else {
     const float nrm = __builtin_sqrtf(g0 * g0 + g1 * g1 + g2 * g2);
     float n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
@@ -230,17 +254,17 @@ __device__ __forceinline__ void store_outputs(const KArgs& a, int64_t p, bool st
     const bool hit = f < a.eps;  // NaN compares false
     if (hit && nrm > 0.0f) {
       const float t = a.eps - f;
-      a.pts_out[3 * p] = x0 + t * n0;
-      a.pts_out[3 * p + 1] = x1 + t * n1;
-      a.pts_out[3 * p + 2] = x2 + t * n2;
+      gview<GV>(a.pts_out)[3 * p] = x0 + t * n0;
+      gview<GV>(a.pts_out)[3 * p + 1] = x1 + t * n1;
+      gview<GV>(a.pts_out)[3 * p + 2] = x2 + t * n2;
     }
-    if (a.sdf) a.sdf[p] = f;
+    if (a.sdf) gview<GV>(a.sdf)[p] = f;
     if (a.normal) {
-      a.normal[3 * p] = n0;
-      a.normal[3 * p + 1] = n1;
-      a.normal[3 * p + 2] = n2;
+      gview<GV>(a.normal)[3 * p] = n0;
+      gview<GV>(a.normal)[3 * p + 1] = n1;
+      gview<GV>(a.normal)[3 * p + 2] = n2;
     }
-    if (a.hit) a.hit[p] = hit ? 1 : 0;
+    if (a.hit) gview<GV>(a.hit)[p] = hit ? 1 : 0;
   }
 }
 

@@ -90,12 +90,11 @@ __device__ __forceinline__ f32x4 unpack4(uint2 u) {
 }
 
 // Address of weight fragment part ps (0 hi, 1 lo) of (K-step kb, local M-tile mt).
-template <class G, class AT>
-__device__ __forceinline__ const AT* wfrag(const unsigned char* layer, int wave, int kb, int mt, int ps,
-                                           int lane) {
-  return reinterpret_cast<const AT*>(layer + (size_t)wave * G::WAVE_BYTES +
-                                     (size_t)((kb * G::MTW + mt) * G::NS_ + ps) * G::FRAG +
-                                     lane * (int)sizeof(AT));
+template <class G, class AT, bool GV>
+__device__ __forceinline__ auto wfrag(const unsigned char* layer, int wave, int kb, int mt, int ps, int lane) {
+  return gview<GV>(reinterpret_cast<const AT*>(layer + (size_t)wave * G::WAVE_BYTES +
+                                               (size_t)((kb * G::MTW + mt) * G::NS_ + ps) * G::FRAG +
+                                               lane * (int)sizeof(AT)));
 }
 
 // v as a BF16 pair: hi = bf16(v), lo = bf16(v - hi).
@@ -111,7 +110,9 @@ __device__ __forceinline__ void split4(f32x4 v, uint2& hi, uint2& lo) {
 template <int W, int PREC, int VAR>
 using GeoP = GeoB<W, PREC == PREC_BF16X3 ? 2 : 1, PREC == PREC_FP8, VAR>;
 
-template <int W, int PREC, int MODE, int VAR>
+// GV: read and write global memory through explicit global-address views
+// (the grouped kernels, whose arguments come from a table in memory).
+template <int W, int PREC, int MODE, int VAR, bool GV = false>
 __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char* lds, int tid) {
   constexpr int NS = PREC == PREC_BF16X3 ? 2 : 1;
   // FP8: E4M3 exchange operands (forward activations stored as r / 4), weights
@@ -154,7 +155,8 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
     const int64_t p = base + tid;
     f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
     if (p < a.n) {
-      float x0 = a.pts_in[3 * p], x1 = a.pts_in[3 * p + 1], x2 = a.pts_in[3 * p + 2];
+      const auto* src = gview<GV>(a.pts_in);
+      float x0 = src[3 * p], x1 = src[3 * p + 1], x2 = src[3 * p + 2];
       to_local(a, x0, x1, x2);
       v[0] = x0;
       v[1] = x1;
@@ -163,7 +165,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
     xs[tid] = v;
   }
   {
-    const f32x4* src = reinterpret_cast<const f32x4*>(a.small);
+    const auto* src = gview<GV>(reinterpret_cast<const f32x4*>(a.small));
     f32x4* dst = reinterpret_cast<f32x4*>(sm);
     for (int i = tid; i < W; i += NT) {  // l1, skf: one float4 per feature
       dst[C_L1 / 4 + i] = src[SL.l1() / 4 + i];
@@ -211,7 +213,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-      for (int ps = 0; ps < NS; ++ps) Aq[s][mt][ps] = *wfrag<G, AT>(fwd, wave, (kb0 + s) & (KB - 1), mt, ps, lane);
+      for (int ps = 0; ps < NS; ++ps) Aq[s][mt][ps] = *wfrag<G, AT, GV>(fwd, wave, (kb0 + s) & (KB - 1), mt, ps, lane);
   __syncthreads();
 
   // r_l of the wave's rows, l = LS+1..L-1, in registers: as the operand tuples
@@ -355,12 +357,12 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-          for (int ps = 0; ps < NS; ++ps) Aq[nk % R][mt][ps] = *wfrag<G, AT>(layer, wave, kbi(nk), mt, ps, lane);
+          for (int ps = 0; ps < NS; ++ps) Aq[nk % R][mt][ps] = *wfrag<G, AT, GV>(layer, wave, kbi(nk), mt, ps, lane);
       } else if (next) {
 #pragma unroll
         for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-          for (int ps = 0; ps < NS; ++ps) Aq[nk % R][mt][ps] = *wfrag<G, AT>(next, wave, kbi(nk - KB), mt, ps, lane);
+          for (int ps = 0; ps < NS; ++ps) Aq[nk % R][mt][ps] = *wfrag<G, AT, GV>(next, wave, kbi(nk - KB), mt, ps, lane);
       }
     };
     auto step = [&](int j, const AT (&B)[NCT][NS]) {
@@ -445,7 +447,7 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
       if constexpr (G::SM_BIAS)
         b = *reinterpret_cast<const f32x4*>(&sm[c_bias(l) + fo]);
       else
-        b = *reinterpret_cast<const f32x4*>(a.small + (l == 1 ? SL.l1g() : SL.bias(l)) + fo);
+        b = *gview<GV>(reinterpret_cast<const f32x4*>(a.small + (l == 1 ? SL.l1g() : SL.bias(l)) + fo));
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[mt][ct] = b;
     }
@@ -624,11 +626,12 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
     f32x4 x = xs[16 * wave + col];
     const int64_t p = base + 16 * wave + col;
     if (a.rigid && p < a.n) {  // the vertex moves in the world frame
-      x[0] = a.pts_in[3 * p];
-      x[1] = a.pts_in[3 * p + 1];
-      x[2] = a.pts_in[3 * p + 2];
+      const auto* src = gview<GV>(a.pts_in);
+      x[0] = src[3 * p];
+      x[1] = src[3 * p + 1];
+      x[2] = src[3 * p + 2];
     }
-    store_outputs<MODE>(a, p, p < a.n && g == 0, s[0] + a.bo, s[1], s[2], s[3], x[0], x[1], x[2]);
+    store_outputs<MODE, GV>(a, p, p < a.n && g == 0, s[0] + a.bo, s[1], s[2], s[3], x[0], x[1], x[2]);
   }
 }
 
@@ -656,7 +659,7 @@ __global__ void K16_WG_SIZE(W) sdf_k16_group(const KArgs* __restrict__ nets,
   const int i = __builtin_amdgcn_readfirstlane(lo);
   __shared__ __attribute__((aligned(16))) unsigned char lds[GeoP<W, PREC, VAR>::LDS_BYTES];
   const KArgs a = nets[i];  // a private copy: loaded once, not again after every barrier
-  k16_tile<W, PREC, MODE, VAR>(a, b - tile_start[i], lds, threadIdx.x);
+  k16_tile<W, PREC, MODE, VAR, true>(a, b - tile_start[i], lds, threadIdx.x);
 }
 
 // Several networks of widths 128-512 (512-thread workgroups) in one
@@ -708,9 +711,9 @@ __global__ void K16_WG_SIZE(256) sdf_k16_persist(const KArgs* __restrict__ nets,
     int tid;
     asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
     switch (__builtin_amdgcn_readfirstlane(tab[n_nets + 1 + i])) {
-      case 128: k16_tile<128, PREC, MODE_PROJECT, 0>(ka, tile, lds, tid); break;
-      case 256: k16_tile<256, PREC, MODE_PROJECT, 0>(ka, tile, lds, tid); break;
-      default: k16_tile<512, PREC, MODE_PROJECT, 0>(ka, tile, lds, tid); break;
+      case 128: k16_tile<128, PREC, MODE_PROJECT, 0, true>(ka, tile, lds, tid); break;
+      case 256: k16_tile<256, PREC, MODE_PROJECT, 0, true>(ka, tile, lds, tid); break;
+      default: k16_tile<512, PREC, MODE_PROJECT, 0, true>(ka, tile, lds, tid); break;
     }
     if (threadIdx.x == 0) next_s = nxt;
     __syncthreads();  // the next item is published; LDS is free for it

@@ -131,7 +131,7 @@ def test_group_rejects_bad_arguments():
         n.close()
 
 
-@pytest.mark.parametrize("mode", ["per_network", "persistent"])
+@pytest.mark.parametrize("mode", ["per_width", "per_network", "persistent"])
 def test_graph_of_thirty_passes_replays_exactly(mode):
     cs = small_set(n_nets=6, total=60_000)
     nets = [B.SdfNet(c["spec"], c["params"], "bf16") for c in cs]

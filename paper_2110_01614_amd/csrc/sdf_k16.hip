@@ -389,7 +389,12 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
         step(j, ownB[j]);
       }
     lds_barrier();
-    AT Bv[2][NCT][NS];  // B operands of K-steps j (in use) and j + 1 (in flight)
+    // B operands of K-steps j (in use) and j + 1 (in flight); single-operand
+    // types at width 512 load each step's operands just before its MFMAs
+    // instead, which keeps their 32-point tile within the registers (the
+    // other wave on the SIMD covers the LDS latency)
+    constexpr int NB = (W == 512 && NS == 1) ? 1 : 2;
+    AT Bv[NB][NCT][NS];
     auto loadB = [&](AT (&dst)[NCT][NS], int j) {
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) {
@@ -418,13 +423,17 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
         }
       }
     };
-    loadB(Bv[0], NOWN);
+    if constexpr (NB == 2) loadB(Bv[0], NOWN);
 #pragma unroll
     for (int j = NOWN; j < KB; ++j) {
       prefetchA(j);
-      if (j + 1 < KB) loadB(Bv[(j + 1 - NOWN) & 1], j + 1);
+      if constexpr (NB == 2) {
+        if (j + 1 < KB) loadB(Bv[(j + 1 - NOWN) & 1], j + 1);
+      } else {
+        loadB(Bv[0], j);
+      }
       __builtin_amdgcn_sched_barrier(0);
-      step(j, Bv[(j - NOWN) & 1]);
+      step(j, Bv[(j - NOWN) & (NB - 1)]);
     }
   };
 

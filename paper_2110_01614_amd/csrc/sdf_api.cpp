@@ -28,8 +28,10 @@ __global__ void pack_fp32_kernel(TrainNet t, const float* P, float* stream, floa
 __global__ void verlet_kernel(float* x, float* xp, int64_t m, float k, float c0, float c1, float c2);
 __global__ void fill_kernel(float* p, int64_t n, float v);
 __global__ void loss_reduce_kernel(const float* terms, int64_t n, float* loss);
+template <int BS>
 __global__ void wgrad_kernel(TrainNet t, const float* E, const float* H, const float* U, int64_t n, int items,
                              int nsplit, float* part, float* grad);
+template <int BS>
 __global__ void wgrad_reduce_kernel(TrainNet t, const float* part, int items, int nsplit, float* grad);
 }  // namespace sdfc
 
@@ -665,10 +667,14 @@ struct TrainLayout {  // byte offsets inside the caller's workspace
   int items, nsplit;  // weight-gradient work items and point slices per item
 };
 
-// Work items of the weight-gradient contraction (wgrad_kernel): 64-row blocks
-// of every layer times 64-column blocks plus the 16-wide tail block.
+// Output blocks of the weight-gradient contraction (wgrad_kernel): 128 x 128
+// from width 128 (eight waves), 64 x 64 below.
+int wgrad_bs(int W) { return W >= 128 ? 128 : 64; }
+
+// Work items of the weight-gradient contraction: row blocks of every layer
+// times column blocks plus the 16-wide tail block.
 int wgrad_items(int W, int L) {
-  const int RB = W / 64, CB = W / 64 + 1;
+  const int RB = W / wgrad_bs(W), CB = RB + 1;
   return RB + (L - 1) * RB * CB + CB;
 }
 
@@ -705,16 +711,16 @@ TrainLayout train_layout(int W, int L, int64_t chunk, int slots, int nsplit) {
   t.loss = o;
   o = up(o + (size_t)chunk * 4);
   t.part = o;
-  if (nsplit > 1) o = up(o + (size_t)nsplit * t.items * 4096 * 4);
+  if (nsplit > 1) o = up(o + (size_t)nsplit * t.items * wgrad_bs(W) * wgrad_bs(W) * 4);
   t.total = o;
   t.chunk = chunk;
   return t;
 }
 
 // Point slices per weight-gradient work item: enough workgroups to fill the
-// GPU several times over, slices of at least 1024 points of a full chunk.
+// GPU a few times over, slices of at least 1024 points of a full chunk.
 int wgrad_splits(int W, int L, int cus) {
-  const int s = 8 * cus / wgrad_items(W, L);
+  const int s = (wgrad_bs(W) == 128 ? 4 : 8) * cus / wgrad_items(W, L);
   return s < 1 ? 1 : (s > 64 ? 64 : s);
 }
 
@@ -815,11 +821,20 @@ int train_run(const sdf_net_desc* desc, int W, int L, int skip, const float* par
   if (W == WW) hipLaunchKernelGGL((sdf_k32<WW, MODE_TRAIN>), grid, dim3(kBlock), 0, s, a);
     KT(64) KT(128) KT(256)
 #undef KT
-    hipLaunchKernelGGL(wgrad_kernel, dim3(items * nsplit), dim3(256), 0, s, t, a.ws_E, a.ws_H, a.ws_U, cn, items,
-                       nsplit, part, grad_params);
-    if (nsplit > 1)
-      hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((items * 4096 + 255) / 256), dim3(256), 0, s, t, part, items,
-                         nsplit, grad_params);
+    const int bs = wgrad_bs(W);
+    if (bs == 128)
+      hipLaunchKernelGGL(wgrad_kernel<128>, dim3(items * nsplit), dim3(128 * 128 / 32), 0, s, t, a.ws_E, a.ws_H,
+                         a.ws_U, cn, items, nsplit, part, grad_params);
+    else
+      hipLaunchKernelGGL(wgrad_kernel<64>, dim3(items * nsplit), dim3(64 * 64 / 32), 0, s, t, a.ws_E, a.ws_H,
+                         a.ws_U, cn, items, nsplit, part, grad_params);
+    if (nsplit > 1) {
+      const dim3 rg((unsigned)(((int64_t)items * bs * bs + 255) / 256));
+      if (bs == 128)
+        hipLaunchKernelGGL(wgrad_reduce_kernel<128>, rg, dim3(256), 0, s, t, part, items, nsplit, grad_params);
+      else
+        hipLaunchKernelGGL(wgrad_reduce_kernel<64>, rg, dim3(256), 0, s, t, part, items, nsplit, grad_params);
+    }
     hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, s, a.ws_loss, cn, loss);
   }
   const hipError_t e = hipGetLastError();

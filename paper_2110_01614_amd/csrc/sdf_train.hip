@@ -97,16 +97,18 @@ __global__ void __launch_bounds__(kLossThreads) loss_reduce_kernel(const float* 
   if (threadIdx.x == 0) loss[0] += part[0];
 }
 
-// Work item `item` of the weight-gradient contraction: hidden layer l
-// (1..L) or the output layer (l = L + 1), a block of 64 output rows and a
-// block of 64 input columns (or the 16-wide tail block: x, y, z, 1, zeros).
+// Work item `item` of the weight-gradient contraction with BS x BS output
+// blocks: hidden layer l (1..L) or the output layer (l = L + 1), a block of
+// BS output rows and a block of BS input columns (or the 16-wide tail block:
+// x, y, z, 1, zeros).
 struct WItem {
   int l, rb, cb;
 };
 
+template <int BS>
 __device__ __forceinline__ WItem wgrad_item(const TrainNet& t, int item) {
   const int W = t.W, L = t.L;
-  const int RB = W / 64, CB = W / 64 + 1;  // row blocks of 64; column blocks of 64 + the 16-wide tail
+  const int RB = W / BS, CB = W / BS + 1;  // row blocks; column blocks + the 16-wide tail
   if (item < RB) return {1, item, CB - 1};  // layer 1: tail columns only
   item -= RB;
   if (item < (L - 1) * RB * CB) return {2 + item / (RB * CB), (item / CB) % RB, item % CB};
@@ -142,48 +144,55 @@ __device__ __forceinline__ int64_t wgrad_dst(const TrainNet& t, int l, int j, in
 // slices of whole 16-point tiles.  Each tile of the block's E rows and H
 // columns is staged in LDS with 16-byte loads (read from global once per
 // workgroup, the next tile's loads in flight while the current one is
-// contracted); wave w contracts rows 16w..16w+15 of the block against its
-// up to 64 columns on v_mfma_f32_16x16x4_f32.  nsplit == 1: grad += the sum
+// contracted); wave w contracts a 32 x 64 part of the BS x BS block on
+// v_mfma_f32_16x16x4_f32 (BS = 128: 8 waves, so every staged byte feeds
+// twice the MFMAs of a 64 x 64 block).  nsplit == 1: grad += the sum
 // directly (one owner per element); otherwise the block is written to
-// part[slice][item][64][64] and wgrad_reduce_kernel adds the slices in a
+// part[slice][item][BS][BS] and wgrad_reduce_kernel adds the slices in a
 // fixed order.
-constexpr int kWgP = 16;  // points per staged tile (small tiles: four workgroups per CU)
-constexpr int kWgS = 80;  // LDS row stride in floats: the four point rows read by one MFMA start 16 banks apart
-__global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __restrict__ E,
-                                                    const float* __restrict__ H,
-                                                    const float* __restrict__ U, int64_t n, int items,
-                                                    int nsplit, float* __restrict__ part,
-                                                    float* __restrict__ grad) {
-  __shared__ __attribute__((aligned(16))) float sE[2][kWgP * kWgS];
-  __shared__ __attribute__((aligned(16))) float sH[2][kWgP * kWgS];
+constexpr int kWgP = 16;  // points per staged tile
+template <int BS>
+__global__ void __launch_bounds__(BS * BS / 32) wgrad_kernel(TrainNet t, const float* __restrict__ E,
+                                                             const float* __restrict__ H,
+                                                             const float* __restrict__ U, int64_t n, int items,
+                                                             int nsplit, float* __restrict__ part,
+                                                             float* __restrict__ grad) {
+  constexpr int NT = BS * BS / 32;        // threads: (BS / 32) x (BS / 64) waves
+  constexpr int WR = BS / 32;             // waves along the rows
+  constexpr int S = BS + 16;              // LDS row stride in floats: the four point rows one MFMA reads start 16 banks apart
+  constexpr int NLD = (BS / 4 * kWgP + NT - 1) / NT;  // float4 loads per thread per operand
+  __shared__ __attribute__((aligned(16))) float sE[2][kWgP * S];
+  __shared__ __attribute__((aligned(16))) float sH[2][kWgP * S];
   const int W = t.W, L = t.L;
   const int item = blockIdx.x % items, slice = blockIdx.x / items;
-  const WItem wi = wgrad_item(t, item);
-  const int l = wi.l, CB = W / 64 + 1;
+  const WItem wi = wgrad_item<BS>(t, item);
+  const int l = wi.l, CB = W / BS + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave % WR, wc = wave / WR;  // this wave: rows 32 wr.., columns 64 wc.. of the block
   const int g = lane >> 4, c16 = lane & 15;
   const bool out_layer = (l == L + 1);
   const bool tail = (wi.cb == CB - 1);
-  const int ncb = tail ? 1 : 4;  // N-tiles of 16 in this block
-  const int col0 = tail ? W : 64 * wi.cb;
+  const int col0 = tail ? W : BS * wi.cb;
   const float* Eb = out_layer ? U : E + (size_t)(l - 1) * n * W;
   const int es = out_layer ? 16 : W;
-  const int er0 = out_layer ? 0 : 64 * wi.rb;  // first staged E column
-  const int ew4 = out_layer ? 4 : 16;          // staged E columns / 4
+  const int er0 = out_layer ? 0 : BS * wi.rb;  // first staged E column
+  const int ew4 = out_layer ? 4 : BS / 4;      // staged E columns / 4
   const float* Hb = H + (size_t)(l - 1) * n * (W + 16);
   const int hs = W + 16;
-  const int hw4 = 4 * ncb;                     // staged H columns / 4
-  // the output layer has one real row: only wave 0 contracts (all waves stage)
-  const bool active = !(out_layer && wave > 0);
+  const int hw4 = tail ? 4 : BS / 4;           // staged H columns / 4
+  // only the staged rows and columns exist: the output layer has 16 rows
+  // (row 0 real), a tail block 16 columns (all waves still stage)
+  const int nrt = out_layer ? 1 : 2, nct = tail ? 1 : 4;
+  const bool active = (wr == 0 || !out_layer) && (wc == 0 || !tail);
   const int64_t tiles = (n + kWgP - 1) / kWgP;
   const int64_t t_lo = tiles * slice / nsplit, t_hi = tiles * (slice + 1) / nsplit;
   const int qE = ew4 * kWgP, qH = hw4 * kWgP;  // float4s of a staged tile
-  float4 rE[kWgP / 16], rH[kWgP / 16];  // up to 64 x kWgP floats of each per 256 threads
+  float4 rE[NLD], rH[NLD];
   auto load = [&](int64_t tile) {
     const int64_t p0 = tile * kWgP;
 #pragma unroll
-    for (int i = 0; i < kWgP / 16; ++i) {
-      const int q = tid + 256 * i;
+    for (int i = 0; i < NLD; ++i) {
+      const int q = tid + NT * i;
       if (q < qE) {
         const int64_t p = p0 + q / ew4;
         rE[i] = p < n ? *reinterpret_cast<const float4*>(Eb + p * es + er0 + 4 * (q % ew4))
@@ -198,14 +207,13 @@ __global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __r
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < kWgP / 16; ++i) {
-      const int q = tid + 256 * i;
-      if (q < qE) *reinterpret_cast<float4*>(&sE[buf][(q / ew4) * kWgS + 4 * (q % ew4)]) = rE[i];
-      if (q < qH) *reinterpret_cast<float4*>(&sH[buf][(q / hw4) * kWgS + 4 * (q % hw4)]) = rH[i];
+    for (int i = 0; i < NLD; ++i) {
+      const int q = tid + NT * i;
+      if (q < qE) *reinterpret_cast<float4*>(&sE[buf][(q / ew4) * S + 4 * (q % ew4)]) = rE[i];
+      if (q < qH) *reinterpret_cast<float4*>(&sH[buf][(q / hw4) * S + 4 * (q % hw4)]) = rH[i];
     }
   };
-  f32x4 acc[4] = {};
-  const int erow = out_layer ? c16 : 16 * wave + c16;  // this lane's E column in the staged tile
+  f32x4 acc[2][4] = {};
   if (t_lo < t_hi) load(t_lo);
   for (int64_t tt = t_lo; tt < t_hi; ++tt) {
     const int buf = (int)((tt - t_lo) & 1);
@@ -217,49 +225,66 @@ __global__ void __launch_bounds__(256) wgrad_kernel(TrainNet t, const float* __r
       const float* h = sH[buf];
 #pragma unroll
       for (int k = 0; k < kWgP; k += 4) {
-        const float a = e[(k + g) * kWgS + erow];
+        const float* er = e + (k + g) * S + 32 * wr + c16;
+        const float* hr = h + (k + g) * S + 64 * wc + c16;
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-          if (nt < ncb) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, h[(k + g) * kWgS + 16 * nt + c16], acc[nt], 0, 0, 0);
+        for (int rt = 0; rt < 2; ++rt) {
+          if (rt < nrt) {
+            const float a = er[16 * rt];
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+              if (ct < nct) acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, hr[16 * ct], acc[rt][ct], 0, 0, 0);
+          }
+        }
       }
     }
   }
   if (!active) return;
-  // acc[nt][i] = sum_p E[p][row0 + 4g + i] H[p][col0 + 16 nt + c16]
-  const int row0 = 64 * wi.rb + 16 * wave;
-  for (int nt = 0; nt < ncb; ++nt) {
+  // acc[rt][ct][i] = sum_p E[p][er0 + 32 wr + 16 rt + 4g + i] H[p][col0 + 64 wc + 16 ct + c16]
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float v = acc[nt][i];
-      if (nsplit > 1) {
-        const int r = 16 * wave + 4 * g + i, c = 16 * nt + c16;
-        part[(((size_t)slice * items + item) * 64 + r) * 64 + c] = v;
-      } else {
-        const int j = (out_layer ? 0 : row0) + 4 * g + i;
-        const int64_t dst = wgrad_dst(t, l, j, col0 + 16 * nt + c16);
-        if (dst >= 0) grad[dst] += v;
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      if (rt >= nrt || ct >= nct) continue;  // (constant indices: acc stays in registers)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float v = acc[rt][ct][i];
+        const int r = 32 * wr + 16 * rt + 4 * g + i, c = 64 * wc + 16 * ct + c16;
+        if (nsplit > 1) {
+          part[(((size_t)slice * items + item) * BS + r) * BS + c] = v;
+        } else {
+          const int64_t dst = wgrad_dst(t, l, (out_layer ? 0 : BS * wi.rb) + r, col0 + c);
+          if (dst >= 0) grad[dst] += v;
+        }
       }
     }
-  }
 }
 
 // grad += sum over the nsplit slices (in slice order) of every work item's
-// 64 x 64 block; one thread per block element.
+// BS x BS block; one thread per block element.
+template <int BS>
 __global__ void __launch_bounds__(256) wgrad_reduce_kernel(TrainNet t, const float* __restrict__ part,
                                                            int items, int nsplit, float* __restrict__ grad) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)items * 4096) return;
-  const int item = (int)(idx >> 12), r = (int)((idx >> 6) & 63), c = (int)(idx & 63);
-  const WItem wi = wgrad_item(t, item);
-  const int W = t.W, CB = W / 64 + 1;
+  if (idx >= (int64_t)items * BS * BS) return;
+  const int item = (int)(idx / (BS * BS)), r = (int)((idx / BS) % BS), c = (int)(idx % BS);
+  const WItem wi = wgrad_item<BS>(t, item);
+  const int W = t.W, CB = W / BS + 1;
   const bool out_layer = (wi.l == t.L + 1), tail = (wi.cb == CB - 1);
   if ((tail && c >= 16) || (out_layer && r >= 16)) return;  // never written
-  const int j = out_layer ? r : 64 * wi.rb + r;
-  const int64_t dst = wgrad_dst(t, wi.l, j, (tail ? W : 64 * wi.cb) + c);
+  const int j = out_layer ? r : BS * wi.rb + r;
+  const int64_t dst = wgrad_dst(t, wi.l, j, (tail ? W : BS * wi.cb) + c);
   if (dst < 0) return;
   float s = 0.0f;
-  for (int q = 0; q < nsplit; ++q) s += part[(((size_t)q * items + item) * 64 + r) * 64 + c];
+  for (int q = 0; q < nsplit; ++q) s += part[(((size_t)q * items + item) * BS + r) * BS + c];
   grad[dst] += s;
 }
+
+template __global__ void wgrad_kernel<64>(TrainNet, const float*, const float*, const float*, int64_t, int, int,
+                                          float*, float*);
+template __global__ void wgrad_kernel<128>(TrainNet, const float*, const float*, const float*, int64_t, int, int,
+                                           float*, float*);
+template __global__ void wgrad_reduce_kernel<64>(TrainNet, const float*, int, int, float*);
+template __global__ void wgrad_reduce_kernel<128>(TrainNet, const float*, int, int, float*);
 
 }  // namespace sdfc

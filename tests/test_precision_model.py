@@ -78,14 +78,37 @@ def test_plain_bf16_misses_and_fp16_meets_the_bar_on_the_geometric_net(cloth):
     assert ef["sdf_max"] <= BAR_F and ef["angle_max"] <= BAR_A, ef
 
 
-def test_cheapest_scheme_found_that_meets_the_bar(cloth):
-    """FP16 forward with the stored activations offset by 1, and a reverse sweep
-    whose two cross terms (W_lo delta_hi + W_hi delta_lo) run on E4M3 operands
-    with one scale per tensor: 1.5 16-bit products per product on average."""
+@pytest.fixture(scope="module")
+def cloth16k():
+    """The same networks on 16,384 other cloth vertices: the target is a
+    maximum over points, so claims that a scheme meets it are checked on a
+    sample four times larger than the GPU tests use."""
+    spec, pn, pts, _ = I.workload_inputs("cloth1m")
+    pg = I.workload_inputs("cloth1m", n=1, init="geometric")[1]
+    P = pts[np.random.default_rng(5).choice(len(pts), 16384, replace=False)]
+    return {name: (spec, prm, P, oracle.mlp_eval(spec, prm, P)) for name, prm in (("normal", pn), ("geometric", pg))}
+
+
+def test_cheapest_scheme_found_that_meets_the_bar(cloth16k):
+    """FP16 main products plus both cross terms (W_lo x_hi + W_hi x_lo) on E4M3
+    operands with a power-of-two scale per 32 elements of K, in both sweeps,
+    with the activations kept for the reverse sweep as FP16 pairs: two 16-bit
+    products per product (the FP8 pass has twice the K at twice the rate)."""
     for name in ("normal", "geometric"):
-        e = _err(cloth, name, "fp16m1", "fp16_t8")
-        assert e["sdf_max"] <= BAR_F and e["angle_max"] <= BAR_A, (name, e)
-    assert (PM.SCHEMES["fp16m1"].cost + PM.SCHEMES["fp16_t8"].cost) / 2 == 1.5
+        e = _err(cloth16k, name, "fp16_c8p", "fp16_c8p")
+        assert e["sdf_max"] <= BAR_F and e["angle_max"] <= 0.5 * BAR_A, (name, e)
+    assert PM.SCHEMES["fp16_c8p"].cost == 2.0
+
+
+def test_a_single_16_bit_stack_misses_the_angle_bar(cloth16k):
+    """The sigmoids of the reverse sweep need more than 16 bits of the stored
+    activation on the N(0, 0.02) network: with one FP16 copy of r - 1 kept,
+    even BF16x3 contractions, or FP16 forward with FP8 cross terms in the
+    reverse sweep, miss 1e-2 rad (on 4096 vertices the latter happens to
+    pass)."""
+    for fwd, rev in (("bf16x3_s16", "bf16x3_s16"), ("fp16m1", "fp16_c8")):
+        e = _err(cloth16k, "normal", fwd, rev)
+        assert e["angle_max"] > BAR_A, (fwd, rev, e)
 
 
 @pytest.mark.parametrize("width", [256, 512])

@@ -74,21 +74,29 @@ __global__ void __launch_bounds__(256) fill_kernel(float* __restrict__ p, int64_
 }
 
 // loss += sum of the chunk's per-point terms: one workgroup of 1024
-// threads, four independent partial sums per thread (so four loads are in
-// flight), then a tree over the threads; the order is fixed.
+// threads; each thread adds its 16-byte groups of terms (four loads in
+// flight per step), thread 0 the n % 4 last terms, then a tree over the
+// threads.  The order is fixed.
 constexpr int kLossThreads = 1024;
 __global__ void __launch_bounds__(kLossThreads) loss_reduce_kernel(const float* __restrict__ terms, int64_t n,
                                                                    float* __restrict__ loss) {
   __shared__ float part[kLossThreads];
-  float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (int64_t i = threadIdx.x; i < n; i += 4 * kLossThreads) {
+  const int64_t n4 = n / 4;
+  const float4* t4 = reinterpret_cast<const float4*>(terms);  // the terms buffer is 256-byte aligned
+  float s = 0.0f;
+  for (int64_t i = threadIdx.x; i < n4; i += 4 * kLossThreads) {
+    float4 v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t j = i + (int64_t)u * kLossThreads;
-      if (j < n) s[u] += terms[j];
+      v[u] = j < n4 ? t4[j] : float4{0.0f, 0.0f, 0.0f, 0.0f};
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += (v[u].x + v[u].y) + (v[u].z + v[u].w);
   }
-  part[threadIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+  if (threadIdx.x == 0)
+    for (int64_t j = 4 * n4; j < n; ++j) s += terms[j];
+  part[threadIdx.x] = s;
   __syncthreads();
   for (int w = kLossThreads / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];

@@ -638,6 +638,12 @@ __device__ __forceinline__ void k16_tile(const KArgs& a, int tile, unsigned char
     for (int w = 1; w < NWV; ++w) s += red[w][16 * wave + col];
     f32x4 x = xs[16 * wave + col];
     const int64_t p = base + 16 * wave + col;
+    if constexpr (F8) {
+      // E4M3 conversion saturates, so a NaN vertex would come out with a
+      // finite f: give it what the other operand types give, f = NaN and a
+      // zero gradient (never a hit, not moved)
+      if (x[0] != x[0] || x[1] != x[1] || x[2] != x[2]) s = f32x4{__builtin_nanf(""), 0.0f, 0.0f, 0.0f};
+    }
     if (a.rigid && p < a.n) {  // the vertex moves in the world frame
       const auto* src = gview<GV>(a.pts_in);
       x[0] = src[3 * p];

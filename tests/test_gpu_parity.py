@@ -336,14 +336,27 @@ def test_plane_net_projects_onto_the_plane_fp32():
     assert np.max(np.abs(f2 - eps)) < 3e-6
 
 
-def test_nan_vertex_is_not_moved_and_bits_kept():
-    spec, params, pts, eps = I.workload_inputs("sphere64", n=100)
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "bf16x3", "fp8"])
+def test_nan_vertex_is_not_moved_and_bits_kept(precision):
+    """A NaN vertex has f = NaN, is never a hit and keeps its bits; the others
+    are unaffected (FP8 runs on a width-128 net, its narrowest)."""
+    if precision == "fp8":
+        spec = I.NetSpec((128,) * 4)
+        params, pts, eps = I.init_geometric(spec, 0), I.uniform_points(100, 1), 0.005
+    else:
+        spec, params, pts, eps = I.workload_inputs("sphere64", n=100)
+    clean = run_gpu(spec, params, pts, precision, eps)
     pts = pts.copy()
     pts[7] = np.nan
-    for precision in ("fp32", "bf16", "bf16x3"):
-        got = run_gpu(spec, params, pts, precision, eps)
-        assert np.isnan(got["sdf"][7]) and got["hit"][7] == 0
-        assert np.array_equal(got["pts"][7].view(np.uint32), pts[7].view(np.uint32))
+    pts[40, 1] = np.nan  # one NaN coordinate is enough
+    got = run_gpu(spec, params, pts, precision, eps)
+    for i in (7, 40):
+        assert np.isnan(got["sdf"][i]) and got["hit"][i] == 0
+        assert np.array_equal(got["pts"][i].view(np.uint32), pts[i].view(np.uint32))
+    rest = np.ones(len(pts), bool)
+    rest[[7, 40]] = False
+    assert np.array_equal(got["sdf"][rest], clean["sdf"][rest])
+    assert np.array_equal(got["pts"][rest], clean["pts"][rest])
 
 
 def test_argument_errors_and_empty_input():

@@ -229,6 +229,7 @@ __global__ void __launch_bounds__(BS * BS / 32) wgrad_kernel(TrainNet t, const f
     __syncthreads();
     if (tt + 1 < t_hi) load(tt + 1);
     if (active) {
+      __builtin_amdgcn_s_setprio(1);  // MFMAs ahead of the other waves' staging (about 1 % of a step)
       const float* e = sE[buf];
       const float* h = sH[buf];
 #pragma unroll
@@ -245,6 +246,7 @@ __global__ void __launch_bounds__(BS * BS / 32) wgrad_kernel(TrainNet t, const f
           }
         }
       }
+      __builtin_amdgcn_s_setprio(0);
     }
   }
   if (!active) return;
